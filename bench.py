@@ -1,0 +1,148 @@
+"""Benchmark of the RD-CNN forward path on one MI355X (arXiv 2102.10340).
+
+Workload (slow growth at scale): one 4096x4096 float32 grid, zero-flux,
+f1 = u - u^3 - v, f2 = 0.1 (u - v), Du = 0.05, Dv = 1, dt = 0.1; x is zero
+except a 16x16 random U[-1,1] centre patch (seed 0); u = v = x.  The job runs
+T = 100000 steps and snapshots (u, v) every 10000 steps into device memory.
+One benchmark step = 10000 time steps + one snapshot, so the default
+``--steps 10`` is the whole job.  Inputs are resident in HBM before timing.
+
+Prints one JSON line: Gcell-updates/s (cells x time steps / s), the roofline of
+the dominant kernel (effective HBM GB/s at 16 B per cell-update, the naive
+traffic of one explicit step), and the CPU oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+R = C = 4096
+T_CHUNK = 10000
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL_UPDATE = 16  # read u, v and write u, v once per explicit step
+FLOPS_PER_CELL_UPDATE = 28  # 7 add + 3 mul + 9 fma of Eq. (1)-(3)
+VALU_OPS_PER_CELL_UPDATE = 19
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: one non-packed VALU op per lane per clock
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(budget_s: float):
+    """The oracle (float32, OpenMP rows) on a bounded sample of the same workload:
+    the 4096x4096 grid and initial state, for as many steps as fit the budget."""
+    import oracle
+    x = W.centre_patch_x(R, C, 16, 0)
+    u, v = oracle.init_state(x, 1.0)
+    t0 = time.perf_counter()
+    u, v = oracle.run(u, v, W.PLAIN_GENE, "zeroflux", 2, "f32")
+    per = (time.perf_counter() - t0) / 2
+    n = int(max(2, min(400, budget_s / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.run(u, v, W.PLAIN_GENE, "zeroflux", n, "f32")
+    dt = time.perf_counter() - t0
+    return {"value": R * C * n / dt / 1e9, "unit": "Gcell-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"4096x4096 slow-growth grid, steps 3..{n + 2} of the job, float32 oracle"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the simulator runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2102_10340_amd import Simulation
+
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(W.centre_patch_x(R, C, 16, 0)).to(dev)
+    sim = Simulation(x, W.PLAIN_GENE, "zeroflux", 1.0)
+    nsnap = args.steps + 1
+    snaps = torch.empty((nsnap, 2, R, C), dtype=torch.float32, device=dev)
+    depth = 8  # steps per pass of the default kernel on this shape
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        sim.step(T_CHUNK)
+    torch.cuda.synchronize()
+    sim_w = sim  # the warm-up advanced the state; the timed job restarts from x
+    sim_w.close()
+    sim = Simulation(x, W.PLAIN_GENE, "zeroflux", 1.0)
+    u0, v0 = snaps[0, 0], snaps[0, 1]
+    from paper_2102_10340_amd._lib import check, lib
+    check(lib.rdcnn_read(sim._h, u0.data_ptr(), v0.data_ptr(), 0))
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t_host = time.perf_counter()
+    ev0.record()
+    for k in range(args.steps):
+        sim.step(T_CHUNK)
+        check(lib.rdcnn_read(sim._h, snaps[k + 1, 0].data_ptr(), snaps[k + 1, 1].data_ptr(), 0))
+    ev1.record()
+    torch.cuda.synchronize()
+    t_host = time.perf_counter() - t_host
+    ms = ev0.elapsed_time(ev1)
+    steps_total = args.steps * T_CHUNK
+    rate = R * C * steps_total / (ms / 1e3)  # cell-updates / s
+    launches = args.steps * (T_CHUNK // depth)
+    launch_s = ms / 1e3 / launches  # upper bound: includes the snapshot copies
+    achieved_gbs = BYTES_PER_CELL_UPDATE * R * C * depth / launch_s / 1e9
+    alive = float(snaps[-1, 0].abs().max())
+
+    out = {
+        "metric": "Gcell-updates/s FP32 forward (slow-growth 4096^2) + % of HBM roofline",
+        "value": rate / 1e9,
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "slow-growth 4096x4096 zero-flux, 16x16 random centre patch, "
+                               "dt=0.1 Du=0.05 Dv=1 f1=u-u^3-v f2=0.1(u-v), T=10000 per step + "
+                               "device snapshot", "time_steps_per_step": T_CHUNK,
+                   "grid": [R, C], "kernel": f"stream_step_kernel<4,{depth}>",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "basis": "16 B per cell-update x R*C*depth cell-updates per launch / mean "
+                              "launch time (HIP events over the timed region)"},
+        "valu": {"achieved_tops": VALU_OPS_PER_CELL_UPDATE * rate / 1e12, "peak_tops": VALU_PEAK_TOPS,
+                 "frac": VALU_OPS_PER_CELL_UPDATE * rate / 1e12 / VALU_PEAK_TOPS,
+                 "tflops": FLOPS_PER_CELL_UPDATE * rate / 1e12},
+        "host_wall_s": t_host,
+        "final_max_abs_u": alive,
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,138 @@
+/*
+ * rdcnn.h -- C ABI of the MI355X (gfx950) library for the FitzHugh-Nagumo
+ * reaction-diffusion cellular nonlinear network (RD-CNN) of Dogaru & Dogaru,
+ * "A Python Framework for Fast Modelling and Simulation of Cellular Nonlinear
+ * Networks and other Finite-difference Time-domain Systems" (arXiv 2102.10340).
+ *
+ * The model (Sec. II.A):
+ *   Eq. (1)  u = v = k_a * x, then T Jacobi explicit-Euler steps
+ *              u+ = u + dt [ f1(u,v) + Du Lap u ]
+ *              v+ = v + dt [ f2(u,v) + Dv Lap v ]
+ *            with the unscaled 5-point Laplacian
+ *              Lap u_ij = u_{i+1,j} + u_{i-1,j} + u_{i,j-1} + u_{i,j+1} - 4 u_ij.
+ *   Eq. (2)  f1 = c u - k3 u^3 - v        (the paper uses k3 = 1/3)
+ *   Eq. (3)  f2 = -eps (u - b v + a)
+ *
+ * Conventions shared by every entry point:
+ *   - A grid has `rows` x `cols` cells (both >= 1), row-major, float32.  A
+ *     state buffer holds the two layers back to back: u plane then v plane,
+ *     i.e. 2 * rows * cols floats, cell (i, j) of u at [i*cols + j] and of v at
+ *     [rows*cols + i*cols + j].
+ *   - Boundary rule: RDCNN_BC_PERIODIC wraps (toroidal, as in the paper's
+ *     kernels); RDCNN_BC_ZEROFLUX lets a missing neighbour copy the edge cell.
+ *   - Every pointer named *_dev is device memory owned by the caller; the
+ *     library never frees it.  Buffers passed to rdcnn_create must stay valid
+ *     until rdcnn_destroy.
+ *   - All device work is enqueued on the caller's HIP stream given at creation
+ *     (a hipStream_t passed as void*; NULL is the default stream) and is
+ *     asynchronous unless stated otherwise.
+ *   - Return value: RDCNN_OK (0) or a negative status.  No call throws or
+ *     aborts.  rdcnn_last_error() gives a message for the calling thread's most
+ *     recent failure.  A handle must not be used from two threads at once.
+ *   - Stability is not enforced: explicit Euler with the unscaled Laplacian
+ *     needs dt * max(Du, Dv) <= 1/4 to stay bounded; larger values are accepted
+ *     and simply diverge, as in the paper's simulator.
+ */
+#ifndef RDCNN_H
+#define RDCNN_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RDCNN_BC_PERIODIC = 0,
+    RDCNN_BC_ZEROFLUX = 1
+};
+
+enum {
+    RDCNN_OK = 0,
+    RDCNN_EINVAL = -1, /* bad argument: null pointer, size < 1, T < 0, non-finite parameter */
+    RDCNN_EHIP = -2,   /* a HIP runtime call or kernel launch failed */
+    RDCNN_ENOMEM = -3, /* host or device allocation of an internal workspace failed */
+    RDCNN_ESTATE = -4  /* call not valid for this handle's state */
+};
+
+/* Gene of Sec. II.A (the paper's Pars vector: dt, a, b, eps, c, Du, Dv) plus
+ * the cubic coefficient k3 of Eq. (2). */
+typedef struct rdcnn_params {
+    float dt;  /* Euler step                         */
+    float a;   /* Eq. (3) offset                     */
+    float b;   /* Eq. (3) v coefficient              */
+    float eps; /* Eq. (3) rate, paper sign: f2 = -eps (u - b v + a) */
+    float c;   /* Eq. (2) linear coefficient         */
+    float k3;  /* Eq. (2) cubic coefficient          */
+    float Du;  /* Eq. (1) diffusion of u             */
+    float Dv;  /* Eq. (1) diffusion of v             */
+} rdcnn_params_t;
+
+typedef struct rdcnn_sim *rdcnn_t;
+
+/*
+ * rdcnn_create -- set up one grid and its initial state (Eq. (1), first line:
+ * u = v = k_a * x, one float32 multiply per cell).
+ *   out       receives the handle (set to NULL on failure)
+ *   rows,cols grid size, >= 1 each
+ *   bc        RDCNN_BC_PERIODIC or RDCNN_BC_ZEROFLUX
+ *   p         parameters (copied); all fields must be finite
+ *   x_dev     rows*cols floats, the initial image x (read once, during the call's
+ *             stream work; it may be freed after the stream reaches it)
+ *   ka        scale k_a (finite)
+ *   buf0_dev, buf1_dev
+ *             two distinct state buffers of 2*rows*cols floats each, the
+ *             ping-pong pair; the initial state is written to buf0_dev
+ *   stream    hipStream_t on which all of this handle's work runs
+ * Errors: RDCNN_EINVAL for a bad argument, RDCNN_EHIP if the launch fails,
+ * RDCNN_ENOMEM if the handle cannot be allocated.
+ */
+int rdcnn_create(rdcnn_t *out, int rows, int cols, int bc, const rdcnn_params_t *p,
+                 const float *x_dev, float ka, float *buf0_dev, float *buf1_dev, void *stream);
+
+/*
+ * rdcnn_step -- advance the grid by T time steps of Eq. (1)-(3) ("for t = 1..T").
+ * T >= 0; T == 0 does nothing.  Asynchronous.  The current state alternates
+ * between the two buffers; rdcnn_current() names the one holding it.
+ */
+int rdcnn_step(rdcnn_t h, long long T);
+
+/*
+ * rdcnn_read -- copy the current state (the paper's snapshot of A and B,
+ * Sec. II.B main loop) into u_dst and v_dst, rows*cols floats each.
+ * dst_is_host != 0: host destinations; the call waits for the stream.
+ * dst_is_host == 0: device destinations; asynchronous on the stream.
+ */
+int rdcnn_read(rdcnn_t h, float *u_dst, float *v_dst, int dst_is_host);
+
+/*
+ * rdcnn_write_state -- replace the current state with (u_dev, v_dev), rows*cols
+ * device floats each (checkpoint restore / resume).  Asynchronous.
+ */
+int rdcnn_write_state(rdcnn_t h, const float *u_dev, const float *v_dev);
+
+/* rdcnn_set_params -- replace the parameters used by later steps. */
+int rdcnn_set_params(rdcnn_t h, const rdcnn_params_t *p);
+
+/* rdcnn_current -- device pointer of the buffer holding the current state. */
+int rdcnn_current(rdcnn_t h, float **state_dev);
+
+/*
+ * rdcnn_set_kernel -- choose how later rdcnn_step calls run (testing and
+ * tuning; the default is chosen per grid shape).
+ *   kind 0: automatic; 1: one thread per cell, one launch per step (reference
+ *   kernel); 2: register-streamed kernel doing up to `depth` steps per HBM pass.
+ *   cols_per_lane 2 (depth 1..16) or 4 (depth 1..12); seg_rows: output rows
+ *   per wavefront, 0 = automatic.  Other fields are ignored for kinds 0 and 1.
+ *   Every setting gives bit-identical states.  Errors: RDCNN_EINVAL.
+ */
+int rdcnn_set_kernel(rdcnn_t h, int kind, int depth, int cols_per_lane, int seg_rows);
+
+/* rdcnn_destroy -- release the handle (not the caller's buffers).  NULL is a no-op. */
+int rdcnn_destroy(rdcnn_t h);
+
+/* Message describing the calling thread's most recent failed call ("" if none). */
+const char *rdcnn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RDCNN_H */

@@ -1,0 +1,225 @@
+// rd_api.hip -- C ABI of the RD-CNN library (declared in include/rdcnn.h).
+//
+// Host-side bookkeeping only: argument checks, the ping-pong state buffers, the
+// choice of kernel and pass depth, and error reporting.  All arithmetic of the
+// method runs in the kernels of rd_forward.hip.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "rd_launch.h"
+#include "rdcnn.h"
+
+struct rdcnn_sim {
+    int R, C, bc;
+    rd::Gene g;
+    float *buf[2];
+    int cur;  // index of the buffer holding the current state
+    hipStream_t stream;
+    int kind;  // 0 automatic, 1 naive, 2 streamed
+    int depth, cpl, seg_rows;
+};
+
+namespace {
+
+thread_local char g_err[512];
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(RDCNN_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_params(const rdcnn_params_t *p)
+{
+    const float v[8] = {p->dt, p->a, p->b, p->eps, p->c, p->k3, p->Du, p->Dv};
+    for (float x : v)
+        if (!isfinite(x)) return false;
+    return true;
+}
+
+rd::Gene to_gene(const rdcnn_params_t *p)
+{
+    rd::Gene g;
+    g.dt = p->dt;
+    g.a = p->a;
+    g.b = p->b;
+    g.eps = p->eps;
+    g.c = p->c;
+    g.k3 = p->k3;
+    g.Du = p->Du;
+    g.Dv = p->Dv;
+    return g;
+}
+
+// Default pass settings for a grid when the caller has not forced any.
+void auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows)
+{
+    *cpl = 4;
+    *depth = 8;
+    *seg_rows = 0;
+    if (h->C < 256) *cpl = 2;
+}
+
+// Run n steps from buf[cur]; flips cur once per pass.
+int run_steps(rdcnn_sim *h, long long n)
+{
+    int kind = h->kind, cpl = h->cpl, depth = h->depth, seg = h->seg_rows;
+    if (kind == 0) {
+        kind = 2;
+        auto_config(h, &cpl, &depth, &seg);
+    }
+    while (n > 0) {
+        hipError_t e;
+        const float *in = h->buf[h->cur];
+        float *out = h->buf[1 - h->cur];
+        long long done;
+        if (kind == 1) {
+            e = rd::launch_naive(in, out, h->R, h->C, h->bc, h->g, h->stream);
+            done = 1;
+        } else {
+            const int k = (int)(n < depth ? n : depth);
+            rd::StreamGeom geom;
+            if (!rd::stream_geometry(h->R, h->C, cpl, k, seg, &geom))
+                return fail(RDCNN_EINVAL, "rdcnn_step: cannot tile %dx%d with cpl=%d depth=%d",
+                            h->R, h->C, cpl, k);
+            e = rd::launch_stream(in, out, h->R, h->C, h->bc, h->g, geom, h->stream);
+            done = k;
+        }
+        if (e != hipSuccess) return hip_fail(e, "rdcnn_step: kernel launch");
+        h->cur = 1 - h->cur;
+        n -= done;
+    }
+    return RDCNN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rdcnn_last_error(void) { return g_err; }
+
+int rdcnn_create(rdcnn_t *out, int rows, int cols, int bc, const rdcnn_params_t *p,
+                 const float *x_dev, float ka, float *buf0_dev, float *buf1_dev, void *stream)
+{
+    if (!out) return fail(RDCNN_EINVAL, "rdcnn_create: out is NULL");
+    *out = nullptr;
+    if (rows < 1 || cols < 1) return fail(RDCNN_EINVAL, "rdcnn_create: grid %dx%d", rows, cols);
+    if ((long long)rows * cols > (1LL << 40))
+        return fail(RDCNN_EINVAL, "rdcnn_create: grid too large");
+    if (bc != RDCNN_BC_PERIODIC && bc != RDCNN_BC_ZEROFLUX)
+        return fail(RDCNN_EINVAL, "rdcnn_create: unknown boundary rule %d", bc);
+    if (!p || !finite_params(p)) return fail(RDCNN_EINVAL, "rdcnn_create: missing or non-finite parameters");
+    if (!isfinite(ka)) return fail(RDCNN_EINVAL, "rdcnn_create: non-finite ka");
+    if (!x_dev || !buf0_dev || !buf1_dev)
+        return fail(RDCNN_EINVAL, "rdcnn_create: NULL device buffer");
+    if (buf0_dev == buf1_dev) return fail(RDCNN_EINVAL, "rdcnn_create: the two state buffers alias");
+    rdcnn_sim *h = new (std::nothrow) rdcnn_sim;
+    if (!h) return fail(RDCNN_ENOMEM, "rdcnn_create: out of host memory");
+    h->R = rows;
+    h->C = cols;
+    h->bc = bc;
+    h->g = to_gene(p);
+    h->buf[0] = buf0_dev;
+    h->buf[1] = buf1_dev;
+    h->cur = 0;
+    h->stream = (hipStream_t)stream;
+    h->kind = 0;
+    h->depth = 0;
+    h->cpl = 0;
+    h->seg_rows = 0;
+    hipError_t e = rd::launch_init(x_dev, ka, buf0_dev, (long long)rows * cols, h->stream);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "rdcnn_create: init launch");
+    }
+    *out = h;
+    return RDCNN_OK;
+}
+
+int rdcnn_step(rdcnn_t h, long long T)
+{
+    if (!h) return fail(RDCNN_EINVAL, "rdcnn_step: NULL handle");
+    if (T < 0) return fail(RDCNN_EINVAL, "rdcnn_step: T = %lld < 0", T);
+    return run_steps(h, T);
+}
+
+int rdcnn_read(rdcnn_t h, float *u_dst, float *v_dst, int dst_is_host)
+{
+    if (!h || !u_dst || !v_dst) return fail(RDCNN_EINVAL, "rdcnn_read: NULL argument");
+    const size_t bytes = sizeof(float) * (size_t)h->R * h->C;
+    const float *s = h->buf[h->cur];
+    const hipMemcpyKind kind = dst_is_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    hipError_t e = hipMemcpyAsync(u_dst, s, bytes, kind, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(v_dst, s + (size_t)h->R * h->C, bytes, kind, h->stream);
+    if (e == hipSuccess && dst_is_host) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "rdcnn_read");
+    return RDCNN_OK;
+}
+
+int rdcnn_write_state(rdcnn_t h, const float *u_dev, const float *v_dev)
+{
+    if (!h || !u_dev || !v_dev) return fail(RDCNN_EINVAL, "rdcnn_write_state: NULL argument");
+    const size_t n = (size_t)h->R * h->C;
+    float *d = h->buf[h->cur];
+    hipError_t e = hipMemcpyAsync(d, u_dev, sizeof(float) * n, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d + n, v_dev, sizeof(float) * n, hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "rdcnn_write_state");
+    return RDCNN_OK;
+}
+
+int rdcnn_set_params(rdcnn_t h, const rdcnn_params_t *p)
+{
+    if (!h || !p) return fail(RDCNN_EINVAL, "rdcnn_set_params: NULL argument");
+    if (!finite_params(p)) return fail(RDCNN_EINVAL, "rdcnn_set_params: non-finite parameter");
+    h->g = to_gene(p);
+    return RDCNN_OK;
+}
+
+int rdcnn_current(rdcnn_t h, float **state_dev)
+{
+    if (!h || !state_dev) return fail(RDCNN_EINVAL, "rdcnn_current: NULL argument");
+    *state_dev = h->buf[h->cur];
+    return RDCNN_OK;
+}
+
+int rdcnn_set_kernel(rdcnn_t h, int kind, int depth, int cols_per_lane, int seg_rows)
+{
+    if (!h) return fail(RDCNN_EINVAL, "rdcnn_set_kernel: NULL handle");
+    if (kind == 0 || kind == 1) {
+        h->kind = kind;
+        return RDCNN_OK;
+    }
+    if (kind != 2) return fail(RDCNN_EINVAL, "rdcnn_set_kernel: unknown kind %d", kind);
+    if (cols_per_lane != 2 && cols_per_lane != 4)
+        return fail(RDCNN_EINVAL, "rdcnn_set_kernel: cols_per_lane %d not in {2,4}", cols_per_lane);
+    if (depth < 1 || depth > rd::max_depth(cols_per_lane))
+        return fail(RDCNN_EINVAL, "rdcnn_set_kernel: depth %d out of range for cols_per_lane %d",
+                    depth, cols_per_lane);
+    if (seg_rows < 0) return fail(RDCNN_EINVAL, "rdcnn_set_kernel: seg_rows < 0");
+    h->kind = 2;
+    h->depth = depth;
+    h->cpl = cols_per_lane;
+    h->seg_rows = seg_rows;
+    return RDCNN_OK;
+}
+
+int rdcnn_destroy(rdcnn_t h)
+{
+    delete h;
+    return RDCNN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+"""Python face of one RD-CNN grid on the GPU (arXiv 2102.10340, Sec. II).
+
+PyTorch only provides the device memory and the stream; the library's kernels
+do every step of Eq. (1)-(3).  Mirrors the paper's workflow: an initial state
+built from an image x and the gene (get_init_state), T iterations of the cell
+kernel, and snapshots of the A (u) and B (v) arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import BC, Params, check, lib
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Simulation:
+    """One rows x cols grid.  ``x`` is a float32 CUDA tensor (the initial image),
+    ``gene`` a mapping with keys dt, a, b, eps, c, k3, Du, Dv, ``bc`` one of
+    "periodic" / "zeroflux".  The state lives in two caller-owned [2, R, C]
+    buffers (u plane, v plane) that ping-pong between steps."""
+
+    def __init__(self, x: torch.Tensor, gene, bc: str = "zeroflux", ka: float = 1.0):
+        if x.dim() != 2 or x.dtype != torch.float32 or not x.is_cuda:
+            raise ValueError("x must be a 2-D float32 CUDA tensor")
+        self.device = x.device
+        self.rows, self.cols = int(x.shape[0]), int(x.shape[1])
+        self.bc = bc
+        self._x = x.contiguous()
+        self.buf = [torch.empty((2, self.rows, self.cols), dtype=torch.float32, device=self.device)
+                    for _ in range(2)]
+        self._h = ctypes.c_void_p()
+        self._params = Params.from_mapping(gene)
+        with torch.cuda.device(self.device):
+            check(lib.rdcnn_create(ctypes.byref(self._h), self.rows, self.cols, BC[bc],
+                                   ctypes.byref(self._params), self._x.data_ptr(), float(ka),
+                                   self.buf[0].data_ptr(), self.buf[1].data_ptr(),
+                                   _stream_handle(self.device)))
+
+    # -- control ---------------------------------------------------------
+    def step(self, T: int) -> "Simulation":
+        """Advance by T steps (asynchronous on the current stream)."""
+        check(lib.rdcnn_step(self._h, int(T)))
+        return self
+
+    def set_params(self, gene) -> None:
+        self._params = Params.from_mapping(gene)
+        check(lib.rdcnn_set_params(self._h, ctypes.byref(self._params)))
+
+    def set_kernel(self, kind: int = 0, depth: int = 0, cols_per_lane: int = 0,
+                   seg_rows: int = 0) -> None:
+        """0 automatic, 1 one-thread-per-cell reference kernel, 2 streamed kernel
+        with `depth` steps per pass (bit-identical results for every choice)."""
+        check(lib.rdcnn_set_kernel(self._h, int(kind), int(depth), int(cols_per_lane),
+                                   int(seg_rows)))
+
+    # -- state -----------------------------------------------------------
+    def state(self) -> torch.Tensor:
+        """View [2, R, C] of the buffer holding the current state (no copy)."""
+        p = ctypes.c_void_p()
+        check(lib.rdcnn_current(self._h, ctypes.byref(p)))
+        for b in self.buf:
+            if b.data_ptr() == p.value:
+                return b
+        raise RuntimeError("current state buffer not found")
+
+    def read(self):
+        """Device copies (u, v) of the current state (the paper's snapshot)."""
+        u = torch.empty((self.rows, self.cols), dtype=torch.float32, device=self.device)
+        v = torch.empty_like(u)
+        check(lib.rdcnn_read(self._h, u.data_ptr(), v.data_ptr(), 0))
+        return u, v
+
+    def read_host(self):
+        """Host numpy copies (u, v); waits for the stream."""
+        u = torch.empty((self.rows, self.cols), dtype=torch.float32, pin_memory=True)
+        v = torch.empty_like(u, pin_memory=True)
+        check(lib.rdcnn_read(self._h, u.data_ptr(), v.data_ptr(), 1))
+        return u.numpy().copy(), v.numpy().copy()
+
+    def write_state(self, u: torch.Tensor, v: torch.Tensor) -> None:
+        u = u.contiguous()
+        v = v.contiguous()
+        if u.shape != (self.rows, self.cols) or v.shape != u.shape:
+            raise ValueError("state shape mismatch")
+        self._keep = (u, v)
+        check(lib.rdcnn_write_state(self._h, u.data_ptr(), v.data_ptr()))
+
+    def close(self) -> None:
+        if self._h:
+            lib.rdcnn_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
