@@ -43,7 +43,29 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--chunk", type=int, default=T_CHUNK,
+                    help="time steps per benchmark step (profiler runs use fewer)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
+                    help="first run a plain device copy of this size (scales HBM counters)")
     return ap.parse_args()
+
+
+def measured_traffic(kernel_prefix: str):
+    """HBM bytes per launch of the kernel from the committed rocprofv3 counter
+    summary, or None if the kernel source changed since it was taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.json"))):
+        with open(path) as f:
+            rec = json.load(f)
+        if rec.get("kernel") != kernel_prefix:
+            continue
+        src = os.path.join(ROOT, rec["source"])
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+                return None
+        return rec["traffic_bytes_per_launch"]
+    return None
 
 
 def cpu_baseline(budget_s: float):
@@ -55,7 +77,7 @@ def cpu_baseline(budget_s: float):
     t0 = time.perf_counter()
     u, v = oracle.run(u, v, W.PLAIN_GENE, "zeroflux", 2, "f32")
     per = (time.perf_counter() - t0) / 2
-    n = int(max(2, min(400, budget_s / max(per, 1e-6))))
+    n = int(max(2, min(2000, budget_s / max(per, 1e-6))))
     t0 = time.perf_counter()
     oracle.run(u, v, W.PLAIN_GENE, "zeroflux", n, "f32")
     dt = time.perf_counter() - t0
@@ -73,23 +95,31 @@ def main():
     import torch
     from paper_2102_10340_amd import Simulation
 
-    dev = torch.device("cuda:0")
-    x = torch.from_numpy(W.centre_patch_x(R, C, 16, 0)).to(dev)
-    sim = Simulation(x, W.PLAIN_GENE, "zeroflux", 1.0)
-    nsnap = args.steps + 1
-    snaps = torch.empty((nsnap, 2, R, C), dtype=torch.float32, device=dev)
-    depth = 8  # steps per pass of the default kernel on this shape
-    torch.cuda.synchronize()
-
-    for _ in range(args.warmup):
-        sim.step(T_CHUNK)
-    torch.cuda.synchronize()
-    sim_w = sim  # the warm-up advanced the state; the timed job restarts from x
-    sim_w.close()
-    sim = Simulation(x, W.PLAIN_GENE, "zeroflux", 1.0)
-    u0, v0 = snaps[0, 0], snaps[0, 1]
     from paper_2102_10340_amd._lib import check, lib
-    check(lib.rdcnn_read(sim._h, u0.data_ptr(), v0.data_ptr(), 0))
+
+    dev = torch.device("cuda:0")
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    x = torch.from_numpy(W.centre_patch_x(R, C, 16, 0)).to(dev)
+    chunk = args.chunk
+    depth = 8  # steps per pass of the default kernel on this shape
+    snaps = torch.empty((args.steps + 1, 2, R, C), dtype=torch.float32, device=dev)
+
+    warm = Simulation(x, W.PLAIN_GENE, "zeroflux", 1.0)
+    for _ in range(args.warmup):
+        warm.step(chunk)
+    torch.cuda.synchronize()
+    warm.close()
+
+    # The timed job starts from the initial state; snapshot 0 is s_0.
+    sim = Simulation(x, W.PLAIN_GENE, "zeroflux", 1.0)
+    check(lib.rdcnn_read(sim._h, snaps[0, 0].data_ptr(), snaps[0, 1].data_ptr(), 0))
     torch.cuda.synchronize()
 
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -97,18 +127,19 @@ def main():
     t_host = time.perf_counter()
     ev0.record()
     for k in range(args.steps):
-        sim.step(T_CHUNK)
+        sim.step(chunk)
         check(lib.rdcnn_read(sim._h, snaps[k + 1, 0].data_ptr(), snaps[k + 1, 1].data_ptr(), 0))
     ev1.record()
     torch.cuda.synchronize()
     t_host = time.perf_counter() - t_host
     ms = ev0.elapsed_time(ev1)
-    steps_total = args.steps * T_CHUNK
+    steps_total = args.steps * chunk
     rate = R * C * steps_total / (ms / 1e3)  # cell-updates / s
-    launches = args.steps * (T_CHUNK // depth)
+    launches = args.steps * (-(-chunk // depth))
     launch_s = ms / 1e3 / launches  # upper bound: includes the snapshot copies
     achieved_gbs = BYTES_PER_CELL_UPDATE * R * C * depth / launch_s / 1e9
     alive = float(snaps[-1, 0].abs().max())
+    traffic = measured_traffic(f"void rd::stream_step_kernel<4, {depth}>")
 
     out = {
         "metric": "Gcell-updates/s FP32 forward (slow-growth 4096^2) + % of HBM roofline",
@@ -125,11 +156,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "slow-growth 4096x4096 zero-flux, 16x16 random centre patch, "
                                "dt=0.1 Du=0.05 Dv=1 f1=u-u^3-v f2=0.1(u-v), T=10000 per step + "
-                               "device snapshot", "time_steps_per_step": T_CHUNK,
+                               "device snapshot", "time_steps_per_step": chunk,
                    "grid": [R, C], "kernel": f"stream_step_kernel<4,{depth}>",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-calibrated)",
+                     "traffic_gbs": None if traffic is None else traffic / launch_s / 1e9,
                      "basis": "16 B per cell-update x R*C*depth cell-updates per launch / mean "
                               "launch time (HIP events over the timed region)"},
         "valu": {"achieved_tops": VALU_OPS_PER_CELL_UPDATE * rate / 1e12, "peak_tops": VALU_PEAK_TOPS,
