@@ -126,6 +126,51 @@ int rdcnn_current(rdcnn_t h, float **state_dev);
  */
 int rdcnn_set_kernel(rdcnn_t h, int kind, int depth, int cols_per_lane, int seg_rows);
 
+/*
+ * rdcnn_step_record -- like rdcnn_step, and also writes the state each of the T
+ * steps starts from: s_t, s_{t+1}, ..., s_{t+T-1} (t = the handle's current
+ * time) to states_dev[0..T-1], each 2*rows*cols floats (u plane, v plane).
+ * These are the states the reverse pass needs.  states_dev: device memory of
+ * at least T*2*rows*cols floats.  Asynchronous.
+ */
+int rdcnn_step_record(rdcnn_t h, long long T, float *states_dev);
+
+/*
+ * rdcnn_adjoint -- reverse pass through S steps of Eq. (1)-(3) (the transpose of
+ * the Jacobian of the explicit-Euler step; the paper gives the forward model
+ * only, Sec. II.A).  For a loss J of the state after the S steps:
+ *   states_dev  the S states the steps started from, as written by
+ *               rdcnn_step_record (states_dev[q] = s_{t0+q}); read only
+ *   adj_dev     [2][rows][cols] floats: on entry (dJ/du, dJ/dv) after the S
+ *               steps, on exit (dJ/du, dJ/dv) before them
+ *   adj_tmp_dev scratch of the same size (contents overwritten)
+ *   dtheta_dev  8 device doubles; dJ/dp of these S steps is ADDED, in the order
+ *               dt, a, b, eps, c, k3, Du, Dv (rdcnn_params_t order)
+ * Uses the handle's current parameters, boundary rule and stream.  S == 0 does
+ * nothing.  The first call on a handle allocates a small device workspace for
+ * per-tile partial sums (8 doubles per tile; freed by rdcnn_destroy).  Results
+ * are deterministic (fixed reduction order).  Asynchronous.
+ * Errors: RDCNN_EINVAL, RDCNN_ENOMEM (workspace), RDCNN_EHIP.
+ */
+int rdcnn_adjoint(rdcnn_t h, const float *states_dev, long long S, float *adj_dev,
+                  float *adj_tmp_dev, double *dtheta_dev);
+
+/*
+ * rdcnn_set_adjoint_kernel -- pass settings for rdcnn_adjoint: `depth` reverse
+ * steps per HBM pass, cols_per_lane 2 (depth 1..8) or 4 (depth 1..6), seg_rows
+ * output rows per wavefront (0 = automatic).  depth = cols_per_lane = 0 restores
+ * the automatic choice.  Errors: RDCNN_EINVAL.
+ */
+int rdcnn_set_adjoint_kernel(rdcnn_t h, int depth, int cols_per_lane, int seg_rows);
+
+/*
+ * rdcnn_init_backward -- chain rule through Eq. (1)'s first line (u = v = k_a x):
+ * gx[i] = ka * (adj[i] + adj[n + i]) for i < n, with adj laid out as
+ * [2][n] (dJ/du then dJ/dv) and gx n floats, both device memory.  Runs on
+ * `stream` (a hipStream_t).  Errors: RDCNN_EINVAL, RDCNN_EHIP.
+ */
+int rdcnn_init_backward(const float *adj_dev, long long n, float ka, float *gx_dev, void *stream);
+
 /* rdcnn_destroy -- release the handle (not the caller's buffers).  NULL is a no-op. */
 int rdcnn_destroy(rdcnn_t h);
 

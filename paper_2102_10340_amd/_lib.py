@@ -51,6 +51,10 @@ _SIGS = {
     "rdcnn_current": [_P, _PP],
     "rdcnn_set_kernel": [_P, _I, _I, _I, _I],
     "rdcnn_destroy": [_P],
+    "rdcnn_step_record": [_P, _LL, _P],
+    "rdcnn_adjoint": [_P, _P, _LL, _P, _P, _P],
+    "rdcnn_set_adjoint_kernel": [_P, _I, _I, _I],
+    "rdcnn_init_backward": [_P, _LL, _F, _P, _P],
 }
 for _name, _args in _SIGS.items():
     _fn = getattr(lib, _name)

@@ -1,0 +1,129 @@
+"""Differentiable RD-CNN runs: torch.autograd.Function wrappers around the
+library's forward, state-recording and adjoint kernels.
+
+The forward keeps one checkpoint every S steps.  The backward walks the
+segments from last to first: it restores a checkpoint, re-runs the segment
+while recording its S states, and runs the adjoint kernel through them.  With S
+near sqrt(T) memory is O(sqrt(T)) states; the default caps S so that one
+segment's states (S x 8 bytes per cell) stay within the GPU's 256 MB last-level
+cache, where the adjoint reads them right after they are written.
+
+Parameters travel as a tensor theta of 8 values in the order
+(dt, a, b, eps, c, k3, Du, Dv), the paper's gene (Sec. II.A) plus the cubic
+coefficient; its gradient is float64 from the library, cast to theta's dtype.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from ._lib import PARAM_FIELDS
+from .sim import Simulation, init_backward
+
+LLC_BYTES = 256 << 20
+
+
+def default_segment(T: int, rows: int, cols: int) -> int:
+    """ceil(sqrt(T)), capped so that a segment of states fits half the last-level cache."""
+    s = max(1, math.ceil(math.sqrt(max(T, 1))))
+    cap = max(1, (LLC_BYTES // 2) // (8 * rows * cols))
+    return max(1, min(s, cap, T if T > 0 else 1))
+
+
+def _gene(theta: torch.Tensor):
+    vals = theta.detach().to("cpu", torch.float64).tolist()
+    if len(vals) != 8:
+        raise ValueError("theta must hold 8 values (dt, a, b, eps, c, k3, Du, Dv)")
+    return dict(zip(PARAM_FIELDS, vals))
+
+
+def _forward(sim: Simulation, T: int, S: int, dev):
+    nseg = -(-T // S) if T > 0 else 0
+    ckpt = torch.empty((max(nseg, 1), 2, sim.rows, sim.cols), dtype=torch.float32, device=dev)
+    for k in range(nseg):
+        sim.read_into(ckpt[k, 0], ckpt[k, 1])
+        sim.step(min(S, T - k * S))
+    u, v = sim.read()
+    return u, v, ckpt, nseg
+
+
+def _backward(sim: Simulation, ckpt, nseg: int, T: int, S: int, gu, gv, dev, kernel=None):
+    R, C = sim.rows, sim.cols
+    adj = torch.empty((2, R, C), dtype=torch.float32, device=dev)
+    adj[0].copy_(gu if gu is not None else torch.zeros((R, C), device=dev))
+    adj[1].copy_(gv if gv is not None else torch.zeros((R, C), device=dev))
+    tmp = torch.empty_like(adj)
+    dtheta = torch.zeros(8, dtype=torch.float64, device=dev)
+    seg = torch.empty((min(S, max(T, 1)), 2, R, C), dtype=torch.float32, device=dev)
+    if kernel is not None:
+        sim.set_adjoint_kernel(*kernel)
+    for k in range(nseg - 1, -1, -1):
+        L = min(S, T - k * S)
+        sim.write_state_packed(ckpt[k])
+        sim.step_record(L, seg)
+        sim.adjoint(seg, L, adj, tmp, dtheta)
+    return adj, dtheta
+
+
+class RDCNNFunction(torch.autograd.Function):
+    """(x, theta) -> (u_T, v_T) with u_0 = v_0 = ka x (Eq. (1)) and T steps."""
+
+    @staticmethod
+    def forward(ctx, x, theta, T: int, bc: str = "zeroflux", ka: float = 1.0, S: int = 0,
+                adj_kernel=None):
+        x = x.detach().contiguous()
+        T = int(T)
+        S = int(S) if S else default_segment(T, x.shape[0], x.shape[1])
+        sim = Simulation(x, _gene(theta), bc, ka)
+        u, v, ckpt, nseg = _forward(sim, T, S, x.device)
+        ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S, ctx.ka = sim, ckpt, nseg, T, S, ka
+        ctx.adj_kernel = adj_kernel
+        ctx.theta_meta = (theta.dtype, theta.device)
+        return u, v
+
+    @staticmethod
+    def backward(ctx, gu, gv):
+        dev = ctx.ckpt.device
+        adj, dtheta = _backward(ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S, gu, gv, dev,
+                                ctx.adj_kernel)
+        gx = init_backward(adj, ctx.ka)
+        ctx.sim.close()
+        dt, dd = ctx.theta_meta
+        return gx, dtheta.to(device=dd, dtype=dt), None, None, None, None, None
+
+
+class RDCNNStateFunction(torch.autograd.Function):
+    """(u0, v0, theta) -> (u_T, v_T): T steps from an explicit state."""
+
+    @staticmethod
+    def forward(ctx, u0, v0, theta, T: int, bc: str = "zeroflux", S: int = 0, adj_kernel=None):
+        u0 = u0.detach().contiguous()
+        v0 = v0.detach().contiguous()
+        T = int(T)
+        S = int(S) if S else default_segment(T, u0.shape[0], u0.shape[1])
+        sim = Simulation.from_state(u0, v0, _gene(theta), bc)
+        u, v, ckpt, nseg = _forward(sim, T, S, u0.device)
+        ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S = sim, ckpt, nseg, T, S
+        ctx.adj_kernel = adj_kernel
+        ctx.theta_meta = (theta.dtype, theta.device)
+        return u, v
+
+    @staticmethod
+    def backward(ctx, gu, gv):
+        dev = ctx.ckpt.device
+        adj, dtheta = _backward(ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S, gu, gv, dev,
+                                ctx.adj_kernel)
+        ctx.sim.close()
+        dt, dd = ctx.theta_meta
+        return adj[0].clone(), adj[1].clone(), dtheta.to(device=dd, dtype=dt), None, None, None, None
+
+
+def simulate(x, theta, T, bc="zeroflux", ka=1.0, S=0):
+    """Differentiable T-step run from u = v = ka x; returns (u_T, v_T)."""
+    return RDCNNFunction.apply(x, theta, T, bc, ka, S, None)
+
+
+def simulate_state(u0, v0, theta, T, bc="zeroflux", S=0):
+    """Differentiable T-step run from (u0, v0); returns (u_T, v_T)."""
+    return RDCNNStateFunction.apply(u0, v0, theta, T, bc, S, None)

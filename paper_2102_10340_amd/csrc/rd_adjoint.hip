@@ -1,0 +1,282 @@
+// rd_adjoint.hip -- reverse pass of the RD-CNN step for gfx950.
+//
+// For a loss J of the final state, with lam' = dJ/du_{t+1} and mu' = dJ/dv_{t+1},
+// the transpose of the Jacobian of one step of Eq. (1)-(3) (Sec. II.A) is
+//   lam_t = lam' + dt [ (c - 3 k3 u_t^2) lam' + Du Lap(lam') - eps mu' ]
+//   mu_t  = mu'  + dt [ -lam' + eps b mu' + Dv Lap(mu') ]
+// (Lap is symmetric for both boundary rules), and the parameter gradients are
+// inner products over cells and steps:
+//   dJ/dDu = dt <Lap lam', u>,  dJ/dDv = dt <Lap mu', v>,  dJ/dc = dt <lam', u>,
+//   dJ/dk3 = -dt <lam', u^3>,   dJ/deps = -dt <mu', u - b v + a>,
+//   dJ/da = -dt eps <mu', 1>,   dJ/db = dt eps <mu', v>,
+//   dJ/ddt = <lam', f1> + <mu', f2> + Du <Lap lam', u> + Dv <Lap mu', v>.
+// Using <lam', Lap u> = <Lap lam', u> the step needs the state only at the cell
+// itself, never its neighbours.
+//
+// adjoint_kernel<CPL, KB> runs KB reverse steps per pass with the same strip /
+// segment / register-window scheme as the forward kernel: (lam, mu) play the role
+// of (u, v), the window of level i holds lam_{t_top-i}, and the state row of
+// s_{t_top-i-1} is read for the row each level makes.  Each lane sums eight
+// products over the output cells it makes (float32 within one pass); the wave
+// reduces them in double and adds them to its tile's slot of a per-tile partial
+// buffer, so every launch and every sum has a fixed order (deterministic).
+// adjoint_finish_kernel folds the partials into the eight gradients.
+#include "rd_launch.h"
+#include "rd_stream.h"
+
+namespace rd {
+
+// The eight sums, in this order.
+enum { S_LLU = 0, S_LMV, S_LU, S_LU3, S_LV, S_MU, S_MV, S_M, NSUM };
+static_assert(NSUM == kAdjSums, "partial buffer layout");
+
+struct AdjArgs {
+    TileArgs t;
+    const float *in;       // (lam, mu) of level 0, [2][R][C]
+    float *out;            // (lam, mu) after KB reverse steps
+    const float *states;   // recorded states, [.][2][R][C]
+    long long q_top;       // state index used by the first reverse step of the pass
+    long long stride;      // floats per state (2 R C)
+    Gene g;
+    double *partial;       // [>= ntiles][NSUM], accumulated
+};
+
+template <int CPL, int KB>
+__global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs A)
+{
+    Tile<CPL> t;
+    if (!t.init(A.t)) return;
+    const int C = A.t.C, R = A.t.R, bc = A.t.bc;
+    const size_t plane = (size_t)R * C;
+    const float *__restrict__ il = A.in;
+    const float *__restrict__ im = A.in + plane;
+    float *__restrict__ ol = A.out;
+    float *__restrict__ om = A.out + plane;
+    const Gene g = A.g;
+    const float c3k = 3.0f * g.k3;
+    const float epsb = g.eps * g.b;
+    const int y0 = t.y0, y1 = t.y1;
+    const int rbase = y0 - KB;
+    const int n_real = y1 - y0 + 2 * KB;
+    const int n_iter = (n_real + 2) / 3 * 3;
+
+    float bl[KB][3][CPL], bm[KB][3][CPL];  // lam, mu windows per level
+    float su[KB][CPL], sv[KB][CPL];        // state row each level needs next
+    float acc[NSUM];
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) acc[k] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) {
+            bl[j][0][e] = bl[j][1][e] = bl[j][2][e] = 0.0f;
+            bm[j][0][e] = bm[j][1][e] = bm[j][2][e] = 0.0f;
+            su[j][e] = sv[j][e] = 0.0f;
+        }
+    {
+        const int rr = map_index(rbase, R, bc);
+        load_row<CPL>(il, rr, C, t, bl[0][0]);
+        load_row<CPL>(im, rr, C, t, bm[0][0]);
+    }
+
+    auto iteration = [&](const int it, const int S) __attribute__((always_inline)) {
+        float tl[CPL], tm[CPL];
+#pragma unroll
+        for (int i = 0; i < KB; ++i) {
+            const Slots sl(S, i);
+            float *dl = i + 1 < KB ? bl[i + 1][sl.cs] : tl;
+            float *dm = i + 1 < KB ? bm[i + 1][sl.cs] : tm;
+            const int m = rbase + it - i - 1;  // row made by level i+1
+            if (it >= 2 * i + 2 && it < n_real) {
+                const float ll = from_left_lane(bl[i][sl.cs][CPL - 1]);
+                const float rl = from_right_lane(bl[i][sl.cs][0]);
+                const float lm = from_left_lane(bm[i][sl.cs][CPL - 1]);
+                const float rm = from_right_lane(bm[i][sl.cs][0]);
+                const bool count = m >= y0 && m < y1;
+#pragma unroll
+                for (int e = 0; e < CPL; ++e) {
+                    const float l = bl[i][sl.cs][e], mu = bm[i][sl.cs][e];
+                    const float lW = e == 0 ? ll : bl[i][sl.cs][e - 1];
+                    const float lE = e == CPL - 1 ? rl : bl[i][sl.cs][e + 1];
+                    const float mW = e == 0 ? lm : bm[i][sl.cs][e - 1];
+                    const float mE = e == CPL - 1 ? rm : bm[i][sl.cs][e + 1];
+                    const float Ll = __builtin_fmaf(
+                        -4.0f, l, (bl[i][sl.ps][e] + bl[i][sl.ns][e]) + (lW + lE));
+                    const float Lm = __builtin_fmaf(
+                        -4.0f, mu, (bm[i][sl.ps][e] + bm[i][sl.ns][e]) + (mW + mE));
+                    const float u = su[i][e], v = sv[i][e];
+                    const float u2 = u * u;
+                    const float gl = __builtin_fmaf(-c3k, u2, g.c) * l;
+                    const float rl_ = __builtin_fmaf(-g.eps, mu, __builtin_fmaf(g.Du, Ll, gl));
+                    dl[e] = __builtin_fmaf(g.dt, rl_, l);
+                    const float rm_ = __builtin_fmaf(g.Dv, Lm, __builtin_fmaf(epsb, mu, -l));
+                    dm[e] = __builtin_fmaf(g.dt, rm_, mu);
+                    if (count && t.owns(A.t, e)) {
+                        acc[S_LLU] = __builtin_fmaf(Ll, u, acc[S_LLU]);
+                        acc[S_LMV] = __builtin_fmaf(Lm, v, acc[S_LMV]);
+                        acc[S_LU] = __builtin_fmaf(l, u, acc[S_LU]);
+                        acc[S_LU3] = __builtin_fmaf(l * u, u2, acc[S_LU3]);
+                        acc[S_LV] = __builtin_fmaf(l, v, acc[S_LV]);
+                        acc[S_MU] = __builtin_fmaf(mu, u, acc[S_MU]);
+                        acc[S_MV] = __builtin_fmaf(mu, v, acc[S_MV]);
+                        acc[S_M] += mu;
+                    }
+                }
+            }
+            // The state row this level needs at the next iteration (level i
+            // works from it = 2i+2 to n_real-1).
+            if (it + 1 >= 2 * i + 2 && it + 1 < n_real) {
+                const float *s = A.states + (A.q_top - i) * A.stride;
+                const int rr = map_index(m + 1, R, bc);
+                load_row<CPL>(s, rr, C, t, su[i]);
+                load_row<CPL>(s + plane, rr, C, t, sv[i]);
+            }
+            if (i == 0) {
+                const int rr = map_index(rbase + it + 1, R, bc);
+                load_row<CPL>(il, rr, C, t, bl[0][sl.ps]);
+                load_row<CPL>(im, rr, C, t, bm[0][sl.ps]);
+            }
+        }
+        const int m = rbase + it - KB;
+        if (m >= y0 && m < y1) {
+            store_row<CPL>(ol, m, C, t, tl);
+            store_row<CPL>(om, m, C, t, tm);
+        }
+    };
+
+    for (int it = 0; it < n_iter; it += 3) {
+        iteration(it, 0);
+        iteration(it + 1, 1);
+        iteration(it + 2, 2);
+    }
+
+    // Wave reduction in double, fixed butterfly order; lane 0 adds to the tile.
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) {
+        double s = (double)acc[k];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (threadIdx.x == 0) A.partial[(size_t)t.tile * NSUM + k] += s;
+    }
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(double *p, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// One workgroup: sums the per-tile partials in a fixed order and adds the
+// gradients (order dt, a, b, eps, c, k3, Du, Dv) to dtheta.
+__global__ __launch_bounds__(256) void adjoint_finish_kernel(const double *partial, int ntiles,
+                                                             Gene g, double *dtheta)
+{
+    __shared__ double red[NSUM][256];
+    double s[NSUM];
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) s[k] = 0.0;
+    for (int i = threadIdx.x; i < ntiles; i += 256)
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k) s[k] += partial[(size_t)i * NSUM + k];
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) red[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < NSUM; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double dt = g.dt, a = g.a, b = g.b, eps = g.eps, c = g.c, k3 = g.k3;
+        const double Du = g.Du, Dv = g.Dv;
+        const double LLU = red[S_LLU][0], LMV = red[S_LMV][0], LU = red[S_LU][0];
+        const double LU3 = red[S_LU3][0], LV = red[S_LV][0], MU = red[S_MU][0];
+        const double MV = red[S_MV][0], M = red[S_M][0];
+        const double res = MU - b * MV + a * M;  // <mu', u - b v + a>
+        dtheta[0] += c * LU - k3 * LU3 - LV - eps * res + Du * LLU + Dv * LMV;  // dt
+        dtheta[1] += -dt * eps * M;                                             // a
+        dtheta[2] += dt * eps * MV;                                             // b
+        dtheta[3] += -dt * res;                                                 // eps
+        dtheta[4] += dt * LU;                                                   // c
+        dtheta[5] += -dt * LU3;                                                 // k3
+        dtheta[6] += dt * LLU;                                                  // Du
+        dtheta[7] += dt * LMV;                                                  // Dv
+    }
+}
+
+// gx = ka (lam + mu): the chain rule through u = v = ka x.
+__global__ __launch_bounds__(256) void init_backward_kernel(const float *adj, long long n, float ka,
+                                                            float *gx)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        gx[i] = ka * (adj[i] + adj[n + i]);
+}
+
+namespace {
+
+using AdjFn = void (*)(AdjArgs);
+
+template <int CPL, int... Ks>
+constexpr AdjFn pick(int k, std::integer_sequence<int, Ks...>)
+{
+    AdjFn f = nullptr;
+    ((f = (k == Ks + 1) ? &adjoint_kernel<CPL, Ks + 1> : f), ...);
+    return f;
+}
+
+unsigned grid1(long long n)
+{
+    long long b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const float *in, float *out, const float *states, long long q_top,
+                          int R, int C, int bc, const Gene &g, const StreamGeom &geom,
+                          double *partial, hipStream_t s)
+{
+    AdjFn f = nullptr;
+    if (geom.cpl == 4)
+        f = pick<4>(geom.depth, std::make_integer_sequence<int, kMaxAdjDepthCpl4>{});
+    else if (geom.cpl == 2)
+        f = pick<2>(geom.depth, std::make_integer_sequence<int, kMaxAdjDepthCpl2>{});
+    if (!f) return hipErrorInvalidValue;
+    AdjArgs a;
+    a.t = tile_args(R, C, bc, geom);
+    a.in = in;
+    a.out = out;
+    a.states = states;
+    a.q_top = q_top;
+    a.stride = 2LL * R * C;
+    a.g = g;
+    a.partial = partial;
+    hipLaunchKernelGGL(f, dim3((unsigned)(8 * geom.per_xcd)), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double *p, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_kernel, dim3(grid1(n)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_finish(const double *partial, int ntiles, const Gene &g, double *dtheta,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL(adjoint_finish_kernel, dim3(1), dim3(256), 0, s, partial, ntiles, g,
+                       dtheta);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_backward(const float *adj, long long n, float ka, float *gx, hipStream_t s)
+{
+    hipLaunchKernelGGL(init_backward_kernel, dim3(grid1(n)), dim3(256), 0, s, adj, n, ka, gx);
+    return hipGetLastError();
+}
+
+}  // namespace rd

@@ -1,8 +1,9 @@
 // rd_api.hip -- C ABI of the RD-CNN library (declared in include/rdcnn.h).
 //
 // Host-side bookkeeping only: argument checks, the ping-pong state buffers, the
-// choice of kernel and pass depth, and error reporting.  All arithmetic of the
-// method runs in the kernels of rd_forward.hip.
+// choice of kernel and pass depth, the adjoint's partial-sum workspace, and error
+// reporting.  All arithmetic of the method runs in the kernels of rd_forward.hip
+// and rd_adjoint.hip.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -21,6 +22,9 @@ struct rdcnn_sim {
     hipStream_t stream;
     int kind;  // 0 automatic, 1 naive, 2 streamed
     int depth, cpl, seg_rows;
+    int adj_depth, adj_cpl, adj_seg_rows;  // 0: automatic
+    double *partial;                       // adjoint per-tile partial sums
+    long long partial_cap;                 // tiles it can hold
 };
 
 namespace {
@@ -72,9 +76,11 @@ void auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows)
     if (h->C < 256) *cpl = 2;
 }
 
-// Run n steps from buf[cur]; flips cur once per pass.
-int run_steps(rdcnn_sim *h, long long n)
+// Run n steps from buf[cur]; flips cur once per pass.  If rec is not null the
+// state each step starts from is also written to rec[0..n-1] (2*R*C floats each).
+int run_steps(rdcnn_sim *h, long long n, float *rec)
 {
+    long long q = 0;
     int kind = h->kind, cpl = h->cpl, depth = h->depth, seg = h->seg_rows;
     if (kind == 0) {
         kind = 2;
@@ -86,7 +92,11 @@ int run_steps(rdcnn_sim *h, long long n)
         float *out = h->buf[1 - h->cur];
         long long done;
         if (kind == 1) {
-            e = rd::launch_naive(in, out, h->R, h->C, h->bc, h->g, h->stream);
+            e = hipSuccess;
+            if (rec)
+                e = hipMemcpyAsync(rec + q * 2LL * h->R * h->C, in, sizeof(float) * 2 * h->R * h->C,
+                                   hipMemcpyDeviceToDevice, h->stream);
+            if (e == hipSuccess) e = rd::launch_naive(in, out, h->R, h->C, h->bc, h->g, h->stream);
             done = 1;
         } else {
             const int k = (int)(n < depth ? n : depth);
@@ -94,14 +104,22 @@ int run_steps(rdcnn_sim *h, long long n)
             if (!rd::stream_geometry(h->R, h->C, cpl, k, seg, &geom))
                 return fail(RDCNN_EINVAL, "rdcnn_step: cannot tile %dx%d with cpl=%d depth=%d",
                             h->R, h->C, cpl, k);
-            e = rd::launch_stream(in, out, h->R, h->C, h->bc, h->g, geom, h->stream);
+            e = rd::launch_stream(in, out, h->R, h->C, h->bc, h->g, geom, h->stream, rec, q);
             done = k;
         }
         if (e != hipSuccess) return hip_fail(e, "rdcnn_step: kernel launch");
         h->cur = 1 - h->cur;
         n -= done;
+        q += done;
     }
     return RDCNN_OK;
+}
+
+void adj_auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows)
+{
+    *cpl = h->C < 256 ? 2 : 4;
+    *depth = 4;
+    *seg_rows = 0;
 }
 
 }  // namespace
@@ -139,6 +157,11 @@ int rdcnn_create(rdcnn_t *out, int rows, int cols, int bc, const rdcnn_params_t 
     h->depth = 0;
     h->cpl = 0;
     h->seg_rows = 0;
+    h->adj_depth = 0;
+    h->adj_cpl = 0;
+    h->adj_seg_rows = 0;
+    h->partial = nullptr;
+    h->partial_cap = 0;
     hipError_t e = rd::launch_init(x_dev, ka, buf0_dev, (long long)rows * cols, h->stream);
     if (e != hipSuccess) {
         delete h;
@@ -152,7 +175,102 @@ int rdcnn_step(rdcnn_t h, long long T)
 {
     if (!h) return fail(RDCNN_EINVAL, "rdcnn_step: NULL handle");
     if (T < 0) return fail(RDCNN_EINVAL, "rdcnn_step: T = %lld < 0", T);
-    return run_steps(h, T);
+    return run_steps(h, T, nullptr);
+}
+
+int rdcnn_step_record(rdcnn_t h, long long T, float *states_dev)
+{
+    if (!h) return fail(RDCNN_EINVAL, "rdcnn_step_record: NULL handle");
+    if (T < 0) return fail(RDCNN_EINVAL, "rdcnn_step_record: T = %lld < 0", T);
+    if (T > 0 && !states_dev) return fail(RDCNN_EINVAL, "rdcnn_step_record: NULL states buffer");
+    return run_steps(h, T, states_dev);
+}
+
+int rdcnn_set_adjoint_kernel(rdcnn_t h, int depth, int cols_per_lane, int seg_rows)
+{
+    if (!h) return fail(RDCNN_EINVAL, "rdcnn_set_adjoint_kernel: NULL handle");
+    if (depth == 0 && cols_per_lane == 0) {
+        h->adj_depth = h->adj_cpl = h->adj_seg_rows = 0;
+        return RDCNN_OK;
+    }
+    if (cols_per_lane != 2 && cols_per_lane != 4)
+        return fail(RDCNN_EINVAL, "rdcnn_set_adjoint_kernel: cols_per_lane %d not in {2,4}",
+                    cols_per_lane);
+    if (depth < 1 || depth > rd::max_adj_depth(cols_per_lane))
+        return fail(RDCNN_EINVAL, "rdcnn_set_adjoint_kernel: depth %d out of range", depth);
+    if (seg_rows < 0) return fail(RDCNN_EINVAL, "rdcnn_set_adjoint_kernel: seg_rows < 0");
+    h->adj_depth = depth;
+    h->adj_cpl = cols_per_lane;
+    h->adj_seg_rows = seg_rows;
+    return RDCNN_OK;
+}
+
+int rdcnn_adjoint(rdcnn_t h, const float *states_dev, long long S, float *adj_dev,
+                  float *adj_tmp_dev, double *dtheta_dev)
+{
+    if (!h) return fail(RDCNN_EINVAL, "rdcnn_adjoint: NULL handle");
+    if (S < 0) return fail(RDCNN_EINVAL, "rdcnn_adjoint: S = %lld < 0", S);
+    if (!adj_dev || !adj_tmp_dev || !dtheta_dev || (S > 0 && !states_dev))
+        return fail(RDCNN_EINVAL, "rdcnn_adjoint: NULL argument");
+    if (adj_dev == adj_tmp_dev) return fail(RDCNN_EINVAL, "rdcnn_adjoint: adj buffers alias");
+    if (S == 0) return RDCNN_OK;
+    int cpl = h->adj_cpl, depth = h->adj_depth, seg = h->adj_seg_rows;
+    if (depth == 0) adj_auto_config(h, &cpl, &depth, &seg);
+    // Every pass has `depth` steps except possibly the last; size the partial
+    // buffer for the larger tiling of the two.
+    rd::StreamGeom gfull, glast;
+    const int klast = (int)(S % depth == 0 ? depth : S % depth);
+    if (!rd::stream_geometry(h->R, h->C, cpl, (int)(S < depth ? S : depth), seg, &gfull) ||
+        !rd::stream_geometry(h->R, h->C, cpl, klast, seg, &glast))
+        return fail(RDCNN_EINVAL, "rdcnn_adjoint: cannot tile %dx%d", h->R, h->C);
+    const long long need = gfull.ntiles > glast.ntiles ? gfull.ntiles : glast.ntiles;
+    if (need > h->partial_cap) {
+        if (h->partial) (void)hipFree(h->partial);
+        h->partial = nullptr;
+        h->partial_cap = 0;
+        hipError_t e = hipMalloc((void **)&h->partial, sizeof(double) * rd::kAdjSums * need);
+        if (e != hipSuccess) {
+            h->partial = nullptr;
+            return fail(RDCNN_ENOMEM, "rdcnn_adjoint: partial buffer: %s", hipGetErrorString(e));
+        }
+        h->partial_cap = need;
+    }
+    hipError_t e = rd::launch_zero(h->partial, rd::kAdjSums * need, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint: zero");
+    float *cur = adj_dev, *other = adj_tmp_dev;
+    long long q_top = S - 1, left = S;
+    while (left > 0) {
+        const int k = (int)(left < depth ? left : depth);
+        rd::StreamGeom geom;
+        if (!rd::stream_geometry(h->R, h->C, cpl, k, seg, &geom))
+            return fail(RDCNN_EINVAL, "rdcnn_adjoint: cannot tile %dx%d", h->R, h->C);
+        e = rd::launch_adjoint(cur, other, states_dev, q_top, h->R, h->C, h->bc, h->g, geom,
+                               h->partial, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint: kernel launch");
+        float *tmp = cur;
+        cur = other;
+        other = tmp;
+        q_top -= k;
+        left -= k;
+    }
+    if (cur != adj_dev) {
+        e = hipMemcpyAsync(adj_dev, cur, sizeof(float) * 2 * (size_t)h->R * h->C,
+                           hipMemcpyDeviceToDevice, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint: copy back");
+    }
+    e = rd::launch_adjoint_finish(h->partial, (int)need, h->g, dtheta_dev, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint: finish");
+    return RDCNN_OK;
+}
+
+int rdcnn_init_backward(const float *adj_dev, long long n, float ka, float *gx_dev, void *stream)
+{
+    if (!adj_dev || !gx_dev || n < 0) return fail(RDCNN_EINVAL, "rdcnn_init_backward: bad argument");
+    if (!isfinite(ka)) return fail(RDCNN_EINVAL, "rdcnn_init_backward: non-finite ka");
+    if (n == 0) return RDCNN_OK;
+    hipError_t e = rd::launch_init_backward(adj_dev, n, ka, gx_dev, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rdcnn_init_backward");
+    return RDCNN_OK;
 }
 
 int rdcnn_read(rdcnn_t h, float *u_dst, float *v_dst, int dst_is_host)
@@ -218,6 +336,8 @@ int rdcnn_set_kernel(rdcnn_t h, int kind, int depth, int cols_per_lane, int seg_
 
 int rdcnn_destroy(rdcnn_t h)
 {
+    if (!h) return RDCNN_OK;
+    if (h->partial) (void)hipFree(h->partial);
     delete h;
     return RDCNN_OK;
 }

@@ -19,6 +19,7 @@
 //                       the boundary-extended grid (map_index), so the boundary
 //                       rule costs nothing inside the loop.
 #include "rd_launch.h"
+#include "rd_stream.h"
 
 namespace rd {
 
@@ -84,64 +85,32 @@ hipError_t launch_naive(const float *in, float *out, int R, int C, int bc, const
 // ---------------------------------------------------------------- streamed
 
 struct StreamArgs {
+    TileArgs t;
     const float *in;
     float *out;
-    int R, C, bc;
     Gene g;
-    int wout, kpad, h, nsegs, ntiles, per_xcd;
-    int vec_ok;  // C % CPL == 0: rows of a plane keep CPL-float alignment
+    float *rec;          // recording: state q0+j of the pass goes to rec + (q0+j)*stride
+    long long rec_q0;
+    long long rec_stride;
 };
 
-template <int CPL>
-using vecf = float __attribute__((ext_vector_type(CPL)));
-
-// Load CPL columns of one row: one aligned vector load when the whole strip
-// lies inside the grid, else per column through the boundary map.
-template <int CPL>
-__device__ __forceinline__ void load_row(const float *__restrict__ plane, int rr, int C, bool fast,
-                                         int cx, const int (&mc)[CPL], float (&x)[CPL])
-{
-    const float *row = plane + (size_t)rr * C;
-    if (fast) {
-        const vecf<CPL> t = *reinterpret_cast<const vecf<CPL> *>(row + cx);
-#pragma unroll
-        for (int e = 0; e < CPL; ++e) x[e] = t[e];
-    } else {
-#pragma unroll
-        for (int e = 0; e < CPL; ++e) x[e] = row[mc[e]];
-    }
-}
-
-template <int CPL, int K>
+template <int CPL, int K, bool REC>
 __global__ __launch_bounds__(64) void stream_step_kernel(StreamArgs A)
 {
-    const int tile = xcd_tile(blockIdx.x, A.per_xcd);
-    if (tile >= A.ntiles) return;
-    const int lane = threadIdx.x;
-    const int strip = tile / A.nsegs;
-    const int seg = tile - strip * A.nsegs;
-    const int x0 = strip * A.wout - A.kpad;  // first (extended) column of the strip
-    const int y0 = seg * A.h;                // first output row of the segment
-    const int y1 = min(y0 + A.h, A.R);
-    const int cx = x0 + CPL * lane;          // first column of this lane
-    const int C = A.C, R = A.R, bc = A.bc;
-    const bool fast = A.vec_ok && x0 >= 0 && x0 + 64 * CPL <= C;
-    int mc[CPL];
-#pragma unroll
-    for (int e = 0; e < CPL; ++e) mc[e] = map_index(cx + e, C, bc);
-    const int oc = cx - x0;
-    const bool lane_out = oc >= A.kpad && oc < A.kpad + A.wout && cx < C;
-    const bool lane_vec = lane_out && A.vec_ok && cx + CPL <= C;
-
+    Tile<CPL> t;
+    if (!t.init(A.t)) return;
+    const int C = A.t.C, R = A.t.R, bc = A.t.bc;
     const size_t plane = (size_t)R * C;
     const float *__restrict__ iu = A.in;
     const float *__restrict__ iv = A.in + plane;
     float *__restrict__ ou = A.out;
     float *__restrict__ ov = A.out + plane;
     const Gene g = A.g;
+    const int y0 = t.y0, y1 = t.y1;
 
-    const int rbase = y0 - K;                         // first row read (level 0)
-    const int n_iter = (y1 - y0 + 2 * K + 2) / 3 * 3;  // rows walked, padded to 3
+    const int rbase = y0 - K;                     // first row read (level 0)
+    const int n_real = y1 - y0 + 2 * K;           // rows walked
+    const int n_iter = (n_real + 2) / 3 * 3;      // ... padded to a multiple of 3
 
     // Row q (counted from rbase) of time level j lives in slot q % 3 of level
     // j.  Iteration `it` reads level-0 row it and makes level-(j+1) row it-j-1
@@ -158,62 +127,62 @@ __global__ __launch_bounds__(64) void stream_step_kernel(StreamArgs A)
             for (int e = 0; e < CPL; ++e) bu[j][q][e] = bv[j][q][e] = 0.0f;
     {
         const int rr = map_index(rbase, R, bc);
-        load_row<CPL>(iu, rr, C, fast, cx, mc, bu[0][0]);
-        load_row<CPL>(iv, rr, C, fast, cx, mc, bv[0][0]);
+        load_row<CPL>(iu, rr, C, t, bu[0][0]);
+        load_row<CPL>(iv, rr, C, t, bv[0][0]);
     }
 
     auto iteration = [&](const int it, const int S) __attribute__((always_inline)) {
         float tu[CPL], tv[CPL];  // row it-K of level K (the pass output)
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const int ns = (S - j + 3 * K) % 3;  // slot of level-j row it-j
-            const int cs = (ns + 2) % 3;        // row it-j-1
-            const int ps = (ns + 1) % 3;        // row it-j-2
-            float *du = j + 1 < K ? bu[j + 1][cs] : tu;  // level j+1, row it-j-1
-            float *dv = j + 1 < K ? bv[j + 1][cs] : tv;
-            if (it >= 2 * j + 2) {  // level j+1 has all three input rows from here on
-                const float lu = from_left_lane(bu[j][cs][CPL - 1]);
-                const float ru = from_right_lane(bu[j][cs][0]);
-                const float lv = from_left_lane(bv[j][cs][CPL - 1]);
-                const float rv = from_right_lane(bv[j][cs][0]);
+            const Slots sl(S, j);
+            float *du = j + 1 < K ? bu[j + 1][sl.cs] : tu;  // level j+1, row it-j-1
+            float *dv = j + 1 < K ? bv[j + 1][sl.cs] : tv;
+            // Level j+1 has all three input rows from it = 2j+2 on; rows made
+            // after it = n_real are beyond the segment's cone.
+            if (it >= 2 * j + 2 && it < n_real) {
+                const float lu = from_left_lane(bu[j][sl.cs][CPL - 1]);
+                const float ru = from_right_lane(bu[j][sl.cs][0]);
+                const float lv = from_left_lane(bv[j][sl.cs][CPL - 1]);
+                const float rv = from_right_lane(bv[j][sl.cs][0]);
 #pragma unroll
                 for (int e = 0; e < CPL; ++e) {
-                    const float uW = e == 0 ? lu : bu[j][cs][e - 1];
-                    const float uE = e == CPL - 1 ? ru : bu[j][cs][e + 1];
-                    const float vW = e == 0 ? lv : bv[j][cs][e - 1];
-                    const float vE = e == CPL - 1 ? rv : bv[j][cs][e + 1];
-                    cell_update(g, bu[j][cs][e], bv[j][cs][e], bu[j][ps][e], bu[j][ns][e], uW, uE,
-                                bv[j][ps][e], bv[j][ns][e], vW, vE, du[e], dv[e]);
+                    const float uW = e == 0 ? lu : bu[j][sl.cs][e - 1];
+                    const float uE = e == CPL - 1 ? ru : bu[j][sl.cs][e + 1];
+                    const float vW = e == 0 ? lv : bv[j][sl.cs][e - 1];
+                    const float vE = e == CPL - 1 ? rv : bv[j][sl.cs][e + 1];
+                    cell_update(g, bu[j][sl.cs][e], bv[j][sl.cs][e], bu[j][sl.ps][e],
+                                bu[j][sl.ns][e], uW, uE, bv[j][sl.ps][e], bv[j][sl.ns][e], vW, vE,
+                                du[e], dv[e]);
+                }
+                if (REC && j + 1 < K) {
+                    const int m = rbase + it - j - 1;
+                    if (m >= y0 && m < y1) {
+                        float *r = A.rec + (A.rec_q0 + j + 1) * A.rec_stride;
+                        store_row<CPL>(r, m, C, t, bu[j + 1][sl.cs]);
+                        store_row<CPL>(r + plane, m, C, t, bv[j + 1][sl.cs]);
+                    }
                 }
             }
             if (j == 0) {
+                if (REC) {
+                    const int m = rbase + it;  // level-0 row it
+                    if (m >= y0 && m < y1) {
+                        float *r = A.rec + A.rec_q0 * A.rec_stride;
+                        store_row<CPL>(r, m, C, t, bu[0][sl.ns]);
+                        store_row<CPL>(r + plane, m, C, t, bv[0][sl.ns]);
+                    }
+                }
                 // Level-0 row it-2 is spent: fetch row it+1 into its slot.
                 const int rr = map_index(rbase + it + 1, R, bc);
-                load_row<CPL>(iu, rr, C, fast, cx, mc, bu[0][ps]);
-                load_row<CPL>(iv, rr, C, fast, cx, mc, bv[0][ps]);
+                load_row<CPL>(iu, rr, C, t, bu[0][sl.ps]);
+                load_row<CPL>(iv, rr, C, t, bv[0][sl.ps]);
             }
         }
         const int m = rbase + it - K;  // row of level K now in (tu, tv)
         if (m >= y0 && m < y1) {
-            float *ru_ = ou + (size_t)m * C;
-            float *rv_ = ov + (size_t)m * C;
-            if (lane_vec) {
-                vecf<CPL> a, b;
-#pragma unroll
-                for (int e = 0; e < CPL; ++e) {
-                    a[e] = tu[e];
-                    b[e] = tv[e];
-                }
-                *reinterpret_cast<vecf<CPL> *>(ru_ + cx) = a;
-                *reinterpret_cast<vecf<CPL> *>(rv_ + cx) = b;
-            } else if (lane_out) {
-#pragma unroll
-                for (int e = 0; e < CPL; ++e)
-                    if (cx + e < C) {
-                        ru_[cx + e] = tu[e];
-                        rv_[cx + e] = tv[e];
-                    }
-            }
+            store_row<CPL>(ou, m, C, t, tu);
+            store_row<CPL>(ov, m, C, t, tv);
         }
     };
 
@@ -256,39 +225,54 @@ namespace {
 
 using StreamFn = void (*)(StreamArgs);
 
-template <int CPL, int... Ks>
+template <int CPL, bool REC, int... Ks>
 constexpr StreamFn pick(int k, std::integer_sequence<int, Ks...>)
 {
     StreamFn f = nullptr;
-    ((f = (k == Ks + 1) ? &stream_step_kernel<CPL, Ks + 1> : f), ...);
+    ((f = (k == Ks + 1) ? &stream_step_kernel<CPL, Ks + 1, REC> : f), ...);
     return f;
+}
+
+template <bool REC>
+StreamFn pick_stream(int cpl, int depth)
+{
+    if (cpl == 4) return pick<4, REC>(depth, std::make_integer_sequence<int, kMaxDepthCpl4>{});
+    if (cpl == 2) return pick<2, REC>(depth, std::make_integer_sequence<int, kMaxDepthCpl2>{});
+    return nullptr;
 }
 
 }  // namespace
 
-hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, const Gene &g,
-                         const StreamGeom &geom, hipStream_t s)
+TileArgs tile_args(int R, int C, int bc, const StreamGeom &geom)
 {
-    StreamFn f = nullptr;
-    if (geom.cpl == 4)
-        f = pick<4>(geom.depth, std::make_integer_sequence<int, kMaxDepthCpl4>{});
-    else if (geom.cpl == 2)
-        f = pick<2>(geom.depth, std::make_integer_sequence<int, kMaxDepthCpl2>{});
+    TileArgs t;
+    t.R = R;
+    t.C = C;
+    t.bc = bc;
+    t.wout = geom.wout;
+    t.kpad = geom.kpad;
+    t.h = geom.h;
+    t.nsegs = geom.nsegs;
+    t.ntiles = geom.ntiles;
+    t.per_xcd = geom.per_xcd;
+    t.vec_ok = (C % geom.cpl) == 0;
+    return t;
+}
+
+hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, const Gene &g,
+                         const StreamGeom &geom, hipStream_t s, float *rec, long long rec_q0)
+{
+    StreamFn f = rec ? pick_stream<true>(geom.cpl, geom.depth)
+                     : pick_stream<false>(geom.cpl, geom.depth);
     if (!f) return hipErrorInvalidValue;
     StreamArgs a;
+    a.t = tile_args(R, C, bc, geom);
     a.in = in;
     a.out = out;
-    a.R = R;
-    a.C = C;
-    a.bc = bc;
     a.g = g;
-    a.wout = geom.wout;
-    a.kpad = geom.kpad;
-    a.h = geom.h;
-    a.nsegs = geom.nsegs;
-    a.ntiles = geom.ntiles;
-    a.per_xcd = geom.per_xcd;
-    a.vec_ok = (C % geom.cpl) == 0;
+    a.rec = rec;
+    a.rec_q0 = rec_q0;
+    a.rec_stride = 2LL * R * C;
     hipLaunchKernelGGL(f, dim3((unsigned)(8 * geom.per_xcd)), dim3(64), 0, s, a);
     return hipGetLastError();
 }

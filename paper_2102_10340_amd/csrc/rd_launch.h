@@ -2,6 +2,7 @@
 #pragma once
 
 #include "rd_common.h"
+#include "rd_stream.h"
 
 namespace rd {
 
@@ -11,6 +12,18 @@ constexpr int kMaxDepthCpl2 = 16;
 constexpr int kMaxDepthCpl4 = 12;
 
 inline int max_depth(int cpl) { return cpl == 4 ? kMaxDepthCpl4 : cpl == 2 ? kMaxDepthCpl2 : 0; }
+
+// Same bound for the adjoint kernel (it also keeps one state row per level).
+constexpr int kMaxAdjDepthCpl2 = 8;
+constexpr int kMaxAdjDepthCpl4 = 6;
+
+inline int max_adj_depth(int cpl)
+{
+    return cpl == 4 ? kMaxAdjDepthCpl4 : cpl == 2 ? kMaxAdjDepthCpl2 : 0;
+}
+
+// Number of partial sums the adjoint keeps per tile.
+constexpr int kAdjSums = 8;
 
 // Geometry of one register-streamed pass over an R x C grid.
 struct StreamGeom {
@@ -26,6 +39,9 @@ struct StreamGeom {
 // Returns false if the shape cannot be tiled with these settings.
 bool stream_geometry(int R, int C, int cpl, int depth, int seg_rows, StreamGeom *g);
 
+// Kernel arguments describing the tiling of `geom`.
+TileArgs tile_args(int R, int C, int bc, const StreamGeom &geom);
+
 // u = v = ka * x over n cells (state holds u then v).
 hipError_t launch_init(const float *x, float ka, float *state, long long n, hipStream_t s);
 
@@ -33,8 +49,27 @@ hipError_t launch_init(const float *x, float ka, float *state, long long n, hipS
 hipError_t launch_naive(const float *in, float *out, int R, int C, int bc, const Gene &g,
                         hipStream_t s);
 
-// `geom.depth` steps in one pass of the register-streamed kernel.
+// `geom.depth` steps in one pass of the register-streamed kernel.  If rec is
+// not null, the states the pass steps from (levels 0..depth-1) are also written
+// to rec + (rec_q0 + j) * 2*R*C.
 hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, const Gene &g,
-                         const StreamGeom &geom, hipStream_t s);
+                         const StreamGeom &geom, hipStream_t s, float *rec = nullptr,
+                         long long rec_q0 = 0);
+
+// `geom.depth` reverse steps: (lam, mu) `in` -> `out`, reading states
+// states[q_top], states[q_top-1], ...; adds each tile's eight sums to partial.
+hipError_t launch_adjoint(const float *in, float *out, const float *states, long long q_top,
+                          int R, int C, int bc, const Gene &g, const StreamGeom &geom,
+                          double *partial, hipStream_t s);
+
+hipError_t launch_zero(double *p, long long n, hipStream_t s);
+
+// Fold ntiles rows of partial sums into the eight gradients, added to dtheta.
+hipError_t launch_adjoint_finish(const double *partial, int ntiles, const Gene &g,
+                                 double *dtheta, hipStream_t s);
+
+// gx = ka (lam + mu) over n cells.
+hipError_t launch_init_backward(const float *adj, long long n, float ka, float *gx,
+                                hipStream_t s);
 
 }  // namespace rd

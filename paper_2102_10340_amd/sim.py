@@ -42,11 +42,49 @@ class Simulation:
                                    self.buf[0].data_ptr(), self.buf[1].data_ptr(),
                                    _stream_handle(self.device)))
 
+    @classmethod
+    def from_state(cls, u0: torch.Tensor, v0: torch.Tensor, gene, bc: str = "zeroflux"):
+        """A grid whose state starts at (u0, v0) instead of k_a x."""
+        sim = cls(u0, gene, bc, 1.0)
+        sim.write_state(u0, v0)
+        return sim
+
     # -- control ---------------------------------------------------------
     def step(self, T: int) -> "Simulation":
         """Advance by T steps (asynchronous on the current stream)."""
         check(lib.rdcnn_step(self._h, int(T)))
         return self
+
+    def step_record(self, T: int, states: torch.Tensor) -> "Simulation":
+        """Advance by T steps and write the state each step starts from into
+        states[0..T-1] (a float32 CUDA tensor of shape [>= T, 2, R, C])."""
+        if T > 0:
+            self._check_states(states, T)
+        check(lib.rdcnn_step_record(self._h, int(T), states.data_ptr() if T > 0 else None))
+        return self
+
+    def adjoint(self, states: torch.Tensor, S: int, adj: torch.Tensor, adj_tmp: torch.Tensor,
+                dtheta: torch.Tensor) -> None:
+        """Reverse pass through S steps recorded in states[0..S-1]: adj [2, R, C]
+        goes from dJ/ds after the steps to dJ/ds before them; dJ/dp (float64 [8],
+        order dt, a, b, eps, c, k3, Du, Dv) is added to dtheta."""
+        if S > 0:
+            self._check_states(states, S)
+        for t in (adj, adj_tmp):
+            if t.shape != (2, self.rows, self.cols) or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError("adjoint buffers must be contiguous float32 [2, R, C]")
+        if dtheta.dtype != torch.float64 or dtheta.numel() != 8 or not dtheta.is_cuda:
+            raise ValueError("dtheta must be a CUDA float64 tensor of 8 elements")
+        check(lib.rdcnn_adjoint(self._h, states.data_ptr() if S > 0 else None, int(S),
+                                adj.data_ptr(), adj_tmp.data_ptr(), dtheta.data_ptr()))
+
+    def set_adjoint_kernel(self, depth: int = 0, cols_per_lane: int = 0, seg_rows: int = 0) -> None:
+        check(lib.rdcnn_set_adjoint_kernel(self._h, int(depth), int(cols_per_lane), int(seg_rows)))
+
+    def _check_states(self, states, n):
+        if (states.dtype != torch.float32 or not states.is_contiguous() or states.dim() != 4
+                or states.shape[0] < n or tuple(states.shape[1:]) != (2, self.rows, self.cols)):
+            raise ValueError("states must be contiguous float32 [>= n, 2, R, C]")
 
     def set_params(self, gene) -> None:
         self._params = Params.from_mapping(gene)
@@ -76,6 +114,13 @@ class Simulation:
         check(lib.rdcnn_read(self._h, u.data_ptr(), v.data_ptr(), 0))
         return u, v
 
+    def read_into(self, u_dst: torch.Tensor, v_dst: torch.Tensor) -> None:
+        """Copy the current state into caller-owned device tensors (asynchronous)."""
+        for t in (u_dst, v_dst):
+            if t.shape != (self.rows, self.cols) or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError("destination must be contiguous float32 [R, C]")
+        check(lib.rdcnn_read(self._h, u_dst.data_ptr(), v_dst.data_ptr(), 0))
+
     def read_host(self):
         """Host numpy copies (u, v); waits for the stream."""
         u = torch.empty((self.rows, self.cols), dtype=torch.float32, pin_memory=True)
@@ -91,6 +136,10 @@ class Simulation:
         self._keep = (u, v)
         check(lib.rdcnn_write_state(self._h, u.data_ptr(), v.data_ptr()))
 
+    def write_state_packed(self, s: torch.Tensor) -> None:
+        """Replace the current state with s, a [2, R, C] tensor (u, v)."""
+        self.write_state(s[0], s[1])
+
     def close(self) -> None:
         if self._h:
             lib.rdcnn_destroy(self._h)
@@ -101,3 +150,13 @@ class Simulation:
             self.close()
         except Exception:
             pass
+
+
+def init_backward(adj: torch.Tensor, ka: float, out: torch.Tensor = None) -> torch.Tensor:
+    """Chain rule through u = v = ka x: returns ka (adj[0] + adj[1])."""
+    adj = adj.contiguous()
+    if out is None:
+        out = torch.empty(adj.shape[1:], dtype=torch.float32, device=adj.device)
+    check(lib.rdcnn_init_backward(adj.data_ptr(), adj[0].numel(), float(ka), out.data_ptr(),
+                                  _stream_handle(adj.device)))
+    return out

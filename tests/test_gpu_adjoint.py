@@ -1,0 +1,175 @@
+"""GPU parity of the reverse pass (state recording, adjoint kernel, autograd)
+against the CPU oracle's float64 reverse pass on the same float32 trajectory.
+
+Tolerance: the adjoint runs in float32 on the GPU and float64 in the oracle,
+over the identical float32 trajectory (the recorded states are bit-exact).  The
+adjoint recursion is linear, so its float32 rounding error grows like the
+number of steps times the float32 unit roundoff relative to the adjoint's own
+size: 1e-4 relative (max-norm) leaves an order of magnitude of margin at
+T <= 200 steps, and 1e-3 on the scalar parameter gradients (which also carry
+the float32 per-pass partial sums).  At the full 1024x1024, T = 2000 size the
+bars are relative 1e-3 on scalars and cosine >= 0.9999 on dJ/dx.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BCS = ("periodic", "zeroflux")
+KEYS = oracle.PARAM_ORDER
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    import paper_2102_10340_amd  # noqa: F401
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+def _grad_scale(dp):
+    return max(abs(v) for v in dp.values())
+
+
+def gpu_record(x, gene, bc, T, kernel=None):
+    from paper_2102_10340_amd import Simulation
+    R, C = x.shape
+    sim = Simulation(torch.from_numpy(x).cuda(), gene, bc, 1.0)
+    if kernel is not None:
+        sim.set_kernel(*kernel)
+    states = torch.empty((T, 2, R, C), dtype=torch.float32, device="cuda")
+    sim.step_record(T, states)
+    return sim, states
+
+
+@pytest.mark.parametrize("kernel", [(1, 0, 0, 0), (2, 8, 4, 0), (2, 5, 2, 3), (2, 16, 2, 0)],
+                         ids=lambda k: "k%d_d%d_c%d_h%d" % k)
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", [(1, 1), (5, 9), (40, 300), (129, 257)], ids=lambda s: "%dx%d" % s)
+def test_recorded_states_bitwise(shape, bc, kernel):
+    R, C = shape
+    x = W.uniform_x(R, C, 31 * R + C)
+    g = W.PLAIN_GENE
+    T = 19
+    sim, states = gpu_record(x, g, bc, T, kernel)
+    st = states.cpu().numpy()
+    u, v = oracle.init_state(x, 1.0)
+    for q in range(T):
+        assert np.array_equal(st[q, 0], u) and np.array_equal(st[q, 1], v), q
+        u, v = oracle.run(u, v, g, bc, 1, "f32")
+    uT, vT = sim.read_host()
+    assert np.array_equal(uT, u) and np.array_equal(vT, v)
+    sim.close()
+
+
+def _adjoint_case(R, C, bc, gene, T, kernel, seed=0):
+    x = W.uniform_x(R, C, seed)
+    sim, states = gpu_record(x, gene, bc, T)
+    if kernel is not None:
+        sim.set_adjoint_kernel(*kernel)
+    rng = np.random.default_rng(seed + 1)
+    lam = rng.standard_normal((R, C)).astype(np.float32)
+    mu = rng.standard_normal((R, C)).astype(np.float32)
+    adj = torch.from_numpy(np.stack([lam, mu])).cuda().contiguous()
+    tmp = torch.empty_like(adj)
+    dth = torch.zeros(8, dtype=torch.float64, device="cuda")
+    sim.adjoint(states, T, adj, tmp, dth)
+    got = adj.cpu().numpy()
+    sim.close()
+    l0, m0, dp, _, _ = oracle.grad(x, x, gene, bc, T, lam, mu, traj="f32")
+    return got, dth.cpu().numpy(), l0, m0, dp
+
+
+@pytest.mark.parametrize("kernel", [None, (4, 4, 0), (8, 2, 0), (3, 4, 5), (1, 2, 1), (6, 4, 7)],
+                         ids=lambda k: "auto" if k is None else "d%d_c%d_h%d" % k)
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", [(1, 1), (3, 70), (33, 17), (64, 64), (131, 300)],
+                         ids=lambda s: "%dx%d" % s)
+def test_adjoint_matches_oracle(shape, bc, kernel):
+    R, C = shape
+    g = W.gene(W.PAPER_DEFAULT_GENE, k3=0.45, Du=0.08, Dv=0.6) if bc == "periodic" else \
+        W.gene(Du=0.1, Dv=0.5)
+    T = 37
+    print(f"case shape={shape} bc={bc} adj_kernel={kernel} T={T}", flush=True)
+    got, dth, l0, m0, dp = _adjoint_case(R, C, bc, g, T, kernel)
+    assert _rel(got[0], l0) < 1e-4 and _rel(got[1], m0) < 1e-4, (_rel(got[0], l0), _rel(got[1], m0))
+    scale = _grad_scale(dp)
+    for i, k in enumerate(KEYS):
+        assert abs(dth[i] - dp[k]) <= 1e-3 * max(abs(dp[k]), 1e-3 * scale), (k, dth[i], dp[k])
+
+
+def test_adjoint_deterministic_and_zero_steps():
+    R, C = 70, 190
+    g = W.PLAIN_GENE
+    a = _adjoint_case(R, C, "zeroflux", g, 25, None)
+    b = _adjoint_case(R, C, "zeroflux", g, 25, None)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    from paper_2102_10340_amd import Simulation
+    sim = Simulation(torch.zeros((4, 5), device="cuda"), g, "zeroflux")
+    adj = torch.ones((2, 4, 5), device="cuda")
+    dth = torch.zeros(8, dtype=torch.float64, device="cuda")
+    sim.adjoint(torch.empty(0), 0, adj, torch.empty_like(adj), dth)
+    assert torch.all(adj == 1) and torch.all(dth == 0)
+    sim.close()
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_autograd_function_matches_oracle(bc):
+    """simulate(x, theta) with checkpoint-and-recompute: J = <w, u_T> + <z, v_T>."""
+    from paper_2102_10340_amd import simulate
+    R, C, T = 96, 80, 150
+    g = W.gene(Du=0.07, Dv=0.8, eps=-0.12)
+    x = W.uniform_x(R, C, 4)
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal((R, C)).astype(np.float32)
+    z = rng.standard_normal((R, C)).astype(np.float32)
+    xt = torch.from_numpy(x).cuda().requires_grad_(True)
+    theta = torch.tensor([g[k] for k in KEYS], dtype=torch.float64, requires_grad=True)
+    for S in (0, 1, 7, 150):
+        xt.grad = None
+        theta.grad = None
+        u, v = simulate(xt, theta, T, bc, 1.0, S)
+        J = (u * torch.from_numpy(w).cuda()).sum() + (v * torch.from_numpy(z).cuda()).sum()
+        J.backward()
+        l0, m0, dp, uT, vT = oracle.grad(x, x, g, bc, T, w, z, traj="f32")
+        assert np.array_equal(u.detach().cpu().numpy(), uT.astype(np.float32))
+        gx = xt.grad.cpu().numpy()
+        assert _rel(gx, l0 + m0) < 1e-4
+        scale = _grad_scale(dp)
+        for i, k in enumerate(KEYS):
+            assert abs(theta.grad[i].item() - dp[k]) <= 1e-3 * max(abs(dp[k]), 1e-3 * scale), (S, k)
+
+
+def test_differentiation_workload_full_size():
+    """1024x1024, T = 2000, loss = MSE(u_T, seeded sinusoid-stripe target):
+    dJ/dDu, dJ/dDv, dJ/deps and dJ/dx against the oracle's reverse pass on the
+    same float32 trajectory."""
+    from paper_2102_10340_amd import simulate
+    R = C = 1024
+    T = 2000
+    g = W.PLAIN_GENE
+    x = W.uniform_x(R, C, 0)
+    target = W.stripe_target(R, C, 0)
+    xt = torch.from_numpy(x).cuda().requires_grad_(True)
+    theta = torch.tensor([g[k] for k in KEYS], dtype=torch.float64, requires_grad=True)
+    u, v = simulate(xt, theta, T, "zeroflux")
+    loss = ((u - torch.from_numpy(target).cuda()) ** 2).mean()
+    loss.backward()
+    uT = u.detach().cpu().numpy()
+    lamT = 2.0 * (uT.astype(np.float64) - target) / (R * C)
+    l0, m0, dp, uo, _ = oracle.grad(x, x, g, "zeroflux", T, lamT, np.zeros_like(lamT), traj="f32")
+    assert np.array_equal(uT, uo.astype(np.float32))
+    gx = xt.grad.cpu().numpy().astype(np.float64)
+    ref = l0 + m0
+    cos = float((gx * ref).sum() / np.sqrt((gx * gx).sum() * (ref * ref).sum()))
+    print(f"dJ/dx cosine {cos:.8f}; grads gpu {theta.grad.tolist()} oracle {[dp[k] for k in KEYS]}")
+    assert cos >= 0.9999
+    for i, k in enumerate(KEYS):
+        if k in ("Du", "Dv", "eps"):
+            assert abs(theta.grad[i].item() - dp[k]) <= 1e-3 * abs(dp[k]), (k, theta.grad[i].item(), dp[k])
