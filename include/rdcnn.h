@@ -72,7 +72,7 @@ typedef struct rdcnn_sim *rdcnn_t;
  * rdcnn_create -- set up one grid and its initial state (Eq. (1), first line:
  * u = v = k_a * x, one float32 multiply per cell).
  *   out       receives the handle (set to NULL on failure)
- *   rows,cols grid size, >= 1 each
+ *   rows,cols grid size, >= 1 each, rows*cols < 2^30 (a plane below 4 GiB)
  *   bc        RDCNN_BC_PERIODIC or RDCNN_BC_ZEROFLUX
  *   p         parameters (copied); all fields must be finite
  *   x_dev     rows*cols floats, the initial image x (read once, during the call's
@@ -170,6 +170,59 @@ int rdcnn_set_adjoint_kernel(rdcnn_t h, int depth, int cols_per_lane, int seg_ro
  * `stream` (a hipStream_t).  Errors: RDCNN_EINVAL, RDCNN_EHIP.
  */
 int rdcnn_init_backward(const float *adj_dev, long long n, float ka, float *gx_dev, void *stream);
+
+/* ------------------------------------------------------------ batches
+ * Many grids of uneven size and parameters advanced together: the paper's
+ * parameter-space exploration (Sec. III), where each simulation was run by hand,
+ * one at a time.  Every step of every instance is Eq. (1)-(3) with that
+ * instance's parameters, bit-identical to a single-grid run. */
+typedef struct rdcnn_batch *rdcnn_batch_t;
+
+/*
+ * rdcnn_batch_create -- set up n instances in two packed ping-pong buffers.
+ *   rows[i], cols[i]  size of instance i (>= 1, rows*cols < 2^30)
+ *   offsets[i]        float offset of instance i in each state buffer, a multiple
+ *                     of 64 (256 bytes); the instance occupies 2*rows*cols floats
+ *                     there (u plane, v plane); instances must not overlap
+ *   params[i]         parameters of instance i (copied; finite)
+ *   bc                boundary rule shared by all instances
+ *   x_dev, x_offsets  initial image of instance i at x_dev + x_offsets[i]
+ *                     (rows*cols floats); u = v = ka*x (Eq. (1), first line)
+ *   buf0_dev, buf1_dev, buf_floats
+ *                     the two packed state buffers and their length in floats;
+ *                     the initial states go to buf0_dev
+ *   stream            hipStream_t for all of the batch's work
+ * Host arrays are read during the call only.  Allocates two small device
+ * tables (instances, tiles), freed by rdcnn_batch_destroy.
+ * Errors: RDCNN_EINVAL, RDCNN_ENOMEM, RDCNN_EHIP.
+ */
+int rdcnn_batch_create(rdcnn_batch_t *out, int n, const int *rows, const int *cols,
+                       const long long *offsets, const rdcnn_params_t *params, int bc,
+                       const float *x_dev, const long long *x_offsets, float ka, float *buf0_dev,
+                       float *buf1_dev, long long buf_floats, void *stream);
+
+/* rdcnn_batch_step -- advance every instance by T steps (asynchronous). */
+int rdcnn_batch_step(rdcnn_batch_t b, long long T);
+
+/* rdcnn_batch_current -- the packed buffer holding the current states. */
+int rdcnn_batch_current(rdcnn_batch_t b, float **state_dev);
+
+/*
+ * rdcnn_batch_set_kernel -- steps per pass (depth), cols_per_lane (2 or 4) and
+ * rows per tile (seg_rows, 0 = default) of later steps; all zero restores the
+ * defaults.  Results are bit-identical for every setting.  Errors: RDCNN_EINVAL.
+ */
+int rdcnn_batch_set_kernel(rdcnn_batch_t b, int depth, int cols_per_lane, int seg_rows);
+
+/*
+ * rdcnn_batch_use_graph -- on != 0: rdcnn_batch_step captures the launches of a
+ * T-step run into a HIP graph on first use and replays it afterwards (one graph
+ * launch per call).  Needs a non-default stream.  Errors: RDCNN_EINVAL.
+ */
+int rdcnn_batch_use_graph(rdcnn_batch_t b, int on);
+
+/* rdcnn_batch_destroy -- release the batch (not the caller's buffers).  NULL is a no-op. */
+int rdcnn_batch_destroy(rdcnn_batch_t b);
 
 /* rdcnn_destroy -- release the handle (not the caller's buffers).  NULL is a no-op. */
 int rdcnn_destroy(rdcnn_t h);

@@ -12,7 +12,7 @@ _EXPORTS = {
     "BC": "._lib", "PARAM_FIELDS": "._lib", "Params": "._lib", "RDCNNError": "._lib",
     "LIB_PATH": "._lib", "Simulation": ".sim", "init_backward": ".sim",
     "RDCNNFunction": ".autograd", "RDCNNStateFunction": ".autograd", "simulate": ".autograd",
-    "simulate_state": ".autograd", "default_segment": ".autograd",
+    "simulate_state": ".autograd", "default_segment": ".autograd", "Batch": ".batch",
 }
 
 __all__ = sorted(_EXPORTS)

@@ -1,12 +1,20 @@
 """Differentiable RD-CNN runs: torch.autograd.Function wrappers around the
 library's forward, state-recording and adjoint kernels.
 
-The forward keeps one checkpoint every S steps.  The backward walks the
-segments from last to first: it restores a checkpoint, re-runs the segment
-while recording its S states, and runs the adjoint kernel through them.  With S
-near sqrt(T) memory is O(sqrt(T)) states; the default caps S so that one
-segment's states (S x 8 bytes per cell) stay within the GPU's 256 MB last-level
-cache, where the adjoint reads them right after they are written.
+Two schedules, chosen by S:
+* S = -1, whole trajectory: the forward records all T states (8 bytes per cell
+  and step) and the backward runs the adjoint kernel straight through them, with
+  no recomputation.  An MI355X has 288 GB of HBM, so this is the default whenever
+  the trajectory fits a quarter of the free device memory (16 GiB for
+  1024x1024 x 2000 steps).
+* S > 0, checkpoint-and-recompute: the forward keeps one checkpoint every S
+  steps; the backward walks the segments from last to first, restores a
+  checkpoint, re-runs the segment while recording its S states and runs the
+  adjoint through them.  With S near sqrt(T) memory is O(sqrt(T)) states; the
+  default S is ceil(sqrt(T)) capped so that one segment's states stay within
+  half of the 256 MB last-level cache, where the adjoint reads them right after
+  they are written.
+S = 0 picks the whole trajectory if it fits, else the checkpointed schedule.
 
 Parameters travel as a tensor theta of 8 values in the order
 (dt, a, b, eps, c, k3, Du, Dv), the paper's gene (Sec. II.A) plus the cubic
@@ -31,6 +39,17 @@ def default_segment(T: int, rows: int, cols: int) -> int:
     return max(1, min(s, cap, T if T > 0 else 1))
 
 
+def choose_schedule(T: int, rows: int, cols: int, S: int, device) -> int:
+    """-1 (record the whole trajectory) or a checkpoint spacing > 0."""
+    if S != 0:
+        return S
+    need = 8 * rows * cols * max(T, 1)
+    free, _ = torch.cuda.mem_get_info(device)
+    if need <= free // 4:
+        return -1
+    return default_segment(T, rows, cols)
+
+
 def _gene(theta: torch.Tensor):
     vals = theta.detach().to("cpu", torch.float64).tolist()
     if len(vals) != 8:
@@ -39,6 +58,11 @@ def _gene(theta: torch.Tensor):
 
 
 def _forward(sim: Simulation, T: int, S: int, dev):
+    if S < 0:  # whole trajectory
+        states = torch.empty((max(T, 1), 2, sim.rows, sim.cols), dtype=torch.float32, device=dev)
+        sim.step_record(T, states)
+        u, v = sim.read()
+        return u, v, states, 0
     nseg = -(-T // S) if T > 0 else 0
     ckpt = torch.empty((max(nseg, 1), 2, sim.rows, sim.cols), dtype=torch.float32, device=dev)
     for k in range(nseg):
@@ -55,9 +79,12 @@ def _backward(sim: Simulation, ckpt, nseg: int, T: int, S: int, gu, gv, dev, ker
     adj[1].copy_(gv if gv is not None else torch.zeros((R, C), device=dev))
     tmp = torch.empty_like(adj)
     dtheta = torch.zeros(8, dtype=torch.float64, device=dev)
-    seg = torch.empty((min(S, max(T, 1)), 2, R, C), dtype=torch.float32, device=dev)
     if kernel is not None:
         sim.set_adjoint_kernel(*kernel)
+    if S < 0:  # ckpt holds the whole recorded trajectory
+        sim.adjoint(ckpt, T, adj, tmp, dtheta)
+        return adj, dtheta
+    seg = torch.empty((min(S, max(T, 1)), 2, R, C), dtype=torch.float32, device=dev)
     for k in range(nseg - 1, -1, -1):
         L = min(S, T - k * S)
         sim.write_state_packed(ckpt[k])
@@ -74,7 +101,7 @@ class RDCNNFunction(torch.autograd.Function):
                 adj_kernel=None):
         x = x.detach().contiguous()
         T = int(T)
-        S = int(S) if S else default_segment(T, x.shape[0], x.shape[1])
+        S = choose_schedule(T, x.shape[0], x.shape[1], int(S), x.device)
         sim = Simulation(x, _gene(theta), bc, ka)
         u, v, ckpt, nseg = _forward(sim, T, S, x.device)
         ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S, ctx.ka = sim, ckpt, nseg, T, S, ka
@@ -101,7 +128,7 @@ class RDCNNStateFunction(torch.autograd.Function):
         u0 = u0.detach().contiguous()
         v0 = v0.detach().contiguous()
         T = int(T)
-        S = int(S) if S else default_segment(T, u0.shape[0], u0.shape[1])
+        S = choose_schedule(T, u0.shape[0], u0.shape[1], int(S), u0.device)
         sim = Simulation.from_state(u0, v0, _gene(theta), bc)
         u, v, ckpt, nseg = _forward(sim, T, S, u0.device)
         ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S = sim, ckpt, nseg, T, S

@@ -1,0 +1,92 @@
+"""Python face of a batch of RD-CNN grids (many sizes and parameter sets
+advanced together; the paper's parameter-space exploration, Sec. III).
+
+Argument marshalling only: the library packs nothing on the host side beyond
+computing aligned offsets; every step runs in the batched HIP kernel.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import BC, Params, check, lib
+
+ALIGN = 64  # floats (256 bytes)
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Batch:
+    """Instances given by initial images ``xs`` (2-D float32 CUDA tensors, any
+    sizes) and one gene per instance; shared boundary rule and k_a.  The states
+    live in two packed [total] float32 buffers; ``state(i)`` views instance i."""
+
+    def __init__(self, xs, genes, bc: str = "zeroflux", ka: float = 1.0):
+        if len(xs) != len(genes) or not xs:
+            raise ValueError("need one gene per instance and at least one instance")
+        self.device = xs[0].device
+        self.bc = bc
+        self.shapes = [(int(x.shape[0]), int(x.shape[1])) for x in xs]
+        n = len(xs)
+        offs, xoffs, pos, xpos = [], [], 0, 0
+        for (R, C) in self.shapes:
+            offs.append(pos)
+            xoffs.append(xpos)
+            pos += -(-2 * R * C // ALIGN) * ALIGN
+            xpos += R * C
+        self.offsets = offs
+        self.total = pos
+        self._x = torch.cat([x.contiguous().reshape(-1) for x in xs]).to(torch.float32)
+        self.buf = [torch.empty(self.total, dtype=torch.float32, device=self.device) for _ in range(2)]
+        rows = (ctypes.c_int * n)(*[s[0] for s in self.shapes])
+        cols = (ctypes.c_int * n)(*[s[1] for s in self.shapes])
+        coff = (ctypes.c_longlong * n)(*offs)
+        cxoff = (ctypes.c_longlong * n)(*xoffs)
+        pars = (Params * n)(*[Params.from_mapping(g) for g in genes])
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib.rdcnn_batch_create(ctypes.byref(self._h), n, rows, cols, coff, pars, BC[bc],
+                                         self._x.data_ptr(), cxoff, float(ka),
+                                         self.buf[0].data_ptr(), self.buf[1].data_ptr(),
+                                         self.total, _stream_handle(self.device)))
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def step(self, T: int) -> "Batch":
+        check(lib.rdcnn_batch_step(self._h, int(T)))
+        return self
+
+    def set_kernel(self, depth: int = 0, cols_per_lane: int = 0, seg_rows: int = 0) -> None:
+        check(lib.rdcnn_batch_set_kernel(self._h, int(depth), int(cols_per_lane), int(seg_rows)))
+
+    def use_graph(self, on: bool = True) -> None:
+        check(lib.rdcnn_batch_use_graph(self._h, 1 if on else 0))
+
+    def current(self) -> torch.Tensor:
+        p = ctypes.c_void_p()
+        check(lib.rdcnn_batch_current(self._h, ctypes.byref(p)))
+        for b in self.buf:
+            if b.data_ptr() == p.value:
+                return b
+        raise RuntimeError("current buffer not found")
+
+    def state(self, i: int) -> torch.Tensor:
+        """View [2, R, C] (u, v) of instance i in the current buffer."""
+        R, C = self.shapes[i]
+        o = self.offsets[i]
+        return self.current()[o:o + 2 * R * C].view(2, R, C)
+
+    def close(self) -> None:
+        if self._h:
+            lib.rdcnn_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -16,7 +16,8 @@
 // adjoint_kernel<CPL, KB> runs KB reverse steps per pass with the same strip /
 // segment / register-window scheme as the forward kernel: (lam, mu) play the role
 // of (u, v), the window of level i holds lam_{t_top-i}, and the state row of
-// s_{t_top-i-1} is read for the row each level makes.  Each lane sums eight
+// s_{t_top-i-1} is read for the row each level makes (the pass reads the KB
+// states s_{t_top-KB} .. s_{t_top-1} through one buffer resource).  Each lane sums eight
 // products over the output cells it makes (float32 within one pass); the wave
 // reduces them in double and adds them to its tile's slot of a per-tile partial
 // buffer, so every launch and every sum has a fixed order (deterministic).
@@ -32,26 +33,21 @@ static_assert(NSUM == kAdjSums, "partial buffer layout");
 
 struct AdjArgs {
     TileArgs t;
-    const float *in;       // (lam, mu) of level 0, [2][R][C]
-    float *out;            // (lam, mu) after KB reverse steps
-    const float *states;   // recorded states, [.][2][R][C]
-    long long q_top;       // state index used by the first reverse step of the pass
-    long long stride;      // floats per state (2 R C)
+    const float *in;      // (lam, mu) of level 0, [2][R][C]
+    float *out;           // (lam, mu) after KB reverse steps
+    const float *states;  // the KB states this pass reads, oldest first, [KB][2][R][C]
     Gene g;
-    double *partial;       // [>= ntiles][NSUM], accumulated
+    double *partial;      // [>= ntiles][NSUM], accumulated
 };
 
-template <int CPL, int KB>
-__global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs A)
+template <int CPL, int KB, bool FAST>
+__device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &t)
 {
-    Tile<CPL> t;
-    if (!t.init(A.t)) return;
     const int C = A.t.C, R = A.t.R, bc = A.t.bc;
-    const size_t plane = (size_t)R * C;
-    const float *__restrict__ il = A.in;
-    const float *__restrict__ im = A.in + plane;
-    float *__restrict__ ol = A.out;
-    float *__restrict__ om = A.out + plane;
+    const unsigned pbytes = 4u * (unsigned)R * (unsigned)C;
+    const Buf il(A.in, pbytes), im(A.in + (size_t)R * C, pbytes);
+    const Buf ol(A.out, pbytes), om(A.out + (size_t)R * C, pbytes);
+    const Buf sb(A.states, 2u * (unsigned)KB * pbytes);
     const Gene g = A.g;
     const float c3k = 3.0f * g.k3;
     const float epsb = g.eps * g.b;
@@ -60,8 +56,15 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs A)
     const int n_real = y1 - y0 + 2 * KB;
     const int n_iter = (n_real + 2) / 3 * 3;
 
+    float w[CPL];  // 1 for this lane's output cells, 0 for halo cells
+#pragma unroll
+    for (int e = 0; e < CPL; ++e) w[e] = t.owns(A.t, e);
+
     float bl[KB][3][CPL], bm[KB][3][CPL];  // lam, mu windows per level
-    float su[KB][CPL], sv[KB][CPL];        // state row each level needs next
+    // State rows per level, in the same modulo-3 slots as the window: the row
+    // level i uses at iteration it sits in slot (it-i-1) mod 3 and is fetched
+    // two iterations ahead.
+    float su[KB][3][CPL], sv[KB][3][CPL];
     float acc[NSUM];
 #pragma unroll
     for (int k = 0; k < NSUM; ++k) acc[k] = 0.0f;
@@ -71,12 +74,13 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs A)
         for (int e = 0; e < CPL; ++e) {
             bl[j][0][e] = bl[j][1][e] = bl[j][2][e] = 0.0f;
             bm[j][0][e] = bm[j][1][e] = bm[j][2][e] = 0.0f;
-            su[j][e] = sv[j][e] = 0.0f;
+            su[j][0][e] = su[j][1][e] = su[j][2][e] = 0.0f;
+            sv[j][0][e] = sv[j][1][e] = sv[j][2][e] = 0.0f;
         }
     {
-        const int rr = map_index(rbase, R, bc);
-        load_row<CPL>(il, rr, C, t, bl[0][0]);
-        load_row<CPL>(im, rr, C, t, bm[0][0]);
+        const unsigned ro = row_off(rbase, R, C, bc);
+        load_row<CPL, FAST>(il, ro, t, bl[0][0]);
+        load_row<CPL, FAST>(im, ro, t, bm[0][0]);
     }
 
     auto iteration = [&](const int it, const int S) __attribute__((always_inline)) {
@@ -104,43 +108,45 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs A)
                         -4.0f, l, (bl[i][sl.ps][e] + bl[i][sl.ns][e]) + (lW + lE));
                     const float Lm = __builtin_fmaf(
                         -4.0f, mu, (bm[i][sl.ps][e] + bm[i][sl.ns][e]) + (mW + mE));
-                    const float u = su[i][e], v = sv[i][e];
+                    const float u = su[i][sl.cs][e], v = sv[i][sl.cs][e];
                     const float u2 = u * u;
                     const float gl = __builtin_fmaf(-c3k, u2, g.c) * l;
                     const float rl_ = __builtin_fmaf(-g.eps, mu, __builtin_fmaf(g.Du, Ll, gl));
                     dl[e] = __builtin_fmaf(g.dt, rl_, l);
                     const float rm_ = __builtin_fmaf(g.Dv, Lm, __builtin_fmaf(epsb, mu, -l));
                     dm[e] = __builtin_fmaf(g.dt, rm_, mu);
-                    if (count && t.owns(A.t, e)) {
-                        acc[S_LLU] = __builtin_fmaf(Ll, u, acc[S_LLU]);
-                        acc[S_LMV] = __builtin_fmaf(Lm, v, acc[S_LMV]);
-                        acc[S_LU] = __builtin_fmaf(l, u, acc[S_LU]);
-                        acc[S_LU3] = __builtin_fmaf(l * u, u2, acc[S_LU3]);
-                        acc[S_LV] = __builtin_fmaf(l, v, acc[S_LV]);
-                        acc[S_MU] = __builtin_fmaf(mu, u, acc[S_MU]);
-                        acc[S_MV] = __builtin_fmaf(mu, v, acc[S_MV]);
-                        acc[S_M] += mu;
+                    if (count) {  // halo cells enter with weight 0
+                        const float uw = w[e] * u, vw = w[e] * v;
+                        acc[S_LLU] = __builtin_fmaf(Ll, uw, acc[S_LLU]);
+                        acc[S_LMV] = __builtin_fmaf(Lm, vw, acc[S_LMV]);
+                        acc[S_LU] = __builtin_fmaf(l, uw, acc[S_LU]);
+                        acc[S_LU3] = __builtin_fmaf(l * uw, u2, acc[S_LU3]);
+                        acc[S_LV] = __builtin_fmaf(l, vw, acc[S_LV]);
+                        acc[S_MU] = __builtin_fmaf(mu, uw, acc[S_MU]);
+                        acc[S_MV] = __builtin_fmaf(mu, vw, acc[S_MV]);
+                        acc[S_M] = __builtin_fmaf(w[e], mu, acc[S_M]);
                     }
                 }
             }
-            // The state row this level needs at the next iteration (level i
-            // works from it = 2i+2 to n_real-1).
-            if (it + 1 >= 2 * i + 2 && it + 1 < n_real) {
-                const float *s = A.states + (A.q_top - i) * A.stride;
-                const int rr = map_index(m + 1, R, bc);
-                load_row<CPL>(s, rr, C, t, su[i]);
-                load_row<CPL>(s + plane, rr, C, t, sv[i]);
+            // The state row this level needs two iterations on (level i works
+            // from it = 2i+2 to n_real-1); level i reads state KB-1-i.  Its slot
+            // held the row used one iteration ago.
+            if (it + 2 >= 2 * i + 2 && it + 2 < n_real) {
+                const unsigned o = 2u * (unsigned)(KB - 1 - i) * pbytes + row_off(m + 2, R, C, bc);
+                load_row<CPL, FAST>(sb, o, t, su[i][sl.ps]);
+                load_row<CPL, FAST>(sb, o + pbytes, t, sv[i][sl.ps]);
             }
             if (i == 0) {
-                const int rr = map_index(rbase + it + 1, R, bc);
-                load_row<CPL>(il, rr, C, t, bl[0][sl.ps]);
-                load_row<CPL>(im, rr, C, t, bm[0][sl.ps]);
+                const unsigned ro = row_off(rbase + it + 1, R, C, bc);
+                load_row<CPL, FAST>(il, ro, t, bl[0][sl.ps]);
+                load_row<CPL, FAST>(im, ro, t, bm[0][sl.ps]);
             }
         }
         const int m = rbase + it - KB;
         if (m >= y0 && m < y1) {
-            store_row<CPL>(ol, m, C, t, tl);
-            store_row<CPL>(om, m, C, t, tm);
+            const unsigned o = 4u * (unsigned)m * C;
+            store_row<CPL, FAST>(ol, o, C, t, tl);
+            store_row<CPL, FAST>(om, o, C, t, tm);
         }
     };
 
@@ -158,6 +164,17 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs A)
         for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
         if (threadIdx.x == 0) A.partial[(size_t)t.tile * NSUM + k] += s;
     }
+}
+
+template <int CPL, int KB>
+__global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs A)
+{
+    Tile<CPL> t;
+    if (!t.init(A.t)) return;
+    if (t.fast)
+        adjoint_body<CPL, KB, true>(A, t);
+    else
+        adjoint_body<CPL, KB, false>(A, t);
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(double *p, long long n)
@@ -245,14 +262,12 @@ hipError_t launch_adjoint(const float *in, float *out, const float *states, long
         f = pick<4>(geom.depth, std::make_integer_sequence<int, kMaxAdjDepthCpl4>{});
     else if (geom.cpl == 2)
         f = pick<2>(geom.depth, std::make_integer_sequence<int, kMaxAdjDepthCpl2>{});
-    if (!f) return hipErrorInvalidValue;
+    if (!f || q_top < geom.depth - 1) return hipErrorInvalidValue;
     AdjArgs a;
     a.t = tile_args(R, C, bc, geom);
     a.in = in;
     a.out = out;
-    a.states = states;
-    a.q_top = q_top;
-    a.stride = 2LL * R * C;
+    a.states = states + (q_top - geom.depth + 1) * 2LL * R * C;
     a.g = g;
     a.partial = partial;
     hipLaunchKernelGGL(f, dim3((unsigned)(8 * geom.per_xcd)), dim3(64), 0, s, a);

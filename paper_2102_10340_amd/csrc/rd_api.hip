@@ -28,10 +28,10 @@ struct rdcnn_sim {
 };
 
 namespace {
-
 thread_local char g_err[512];
+}
 
-int fail(int code, const char *fmt, ...)
+int rd::set_error(int code, const char *fmt, ...)
 {
     va_list ap;
     va_start(ap, fmt);
@@ -39,6 +39,10 @@ int fail(int code, const char *fmt, ...)
     va_end(ap);
     return code;
 }
+
+#define fail(...) rd::set_error(__VA_ARGS__)
+
+namespace {
 
 int hip_fail(hipError_t e, const char *what)
 {
@@ -67,13 +71,25 @@ rd::Gene to_gene(const rdcnn_params_t *p)
     return g;
 }
 
-// Default pass settings for a grid when the caller has not forced any.
-void auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows)
+// Default pass settings for a grid when the caller has not forced any (from
+// sweeps on MI355X: wide strips and deep passes pay off only on large grids;
+// smaller grids are latency bound and want more, narrower wavefronts).
+void auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows, bool record)
 {
-    *cpl = 4;
-    *depth = 8;
     *seg_rows = 0;
-    if (h->C < 256) *cpl = 2;
+    if (record) {
+        *cpl = 2;
+        *depth = 8;
+    } else if (h->R >= 2048 && h->C >= 2048) {
+        *cpl = 4;
+        *depth = 8;
+    } else if ((long long)h->R * h->C >= 512LL * 512) {
+        *cpl = 2;
+        *depth = 4;
+    } else {
+        *cpl = 2;
+        *depth = 8;
+    }
 }
 
 // Run n steps from buf[cur]; flips cur once per pass.  If rec is not null the
@@ -84,7 +100,14 @@ int run_steps(rdcnn_sim *h, long long n, float *rec)
     int kind = h->kind, cpl = h->cpl, depth = h->depth, seg = h->seg_rows;
     if (kind == 0) {
         kind = 2;
-        auto_config(h, &cpl, &depth, &seg);
+        auto_config(h, &cpl, &depth, &seg, rec != nullptr);
+    }
+    if (rec && kind == 2) {
+        // A pass's recorded states are addressed through one 4 GiB buffer resource.
+        const long long cap = ((1LL << 32) - 1) / (8LL * h->R * h->C);
+        if (cap < 1)
+            return fail(RDCNN_EINVAL, "rdcnn_step_record: grid too large to record");
+        if (depth > cap) depth = (int)cap;
     }
     while (n > 0) {
         hipError_t e;
@@ -115,9 +138,9 @@ int run_steps(rdcnn_sim *h, long long n, float *rec)
     return RDCNN_OK;
 }
 
-void adj_auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows)
+void adj_auto_config(const rdcnn_sim *, int *cpl, int *depth, int *seg_rows)
 {
-    *cpl = h->C < 256 ? 2 : 4;
+    *cpl = 2;
     *depth = 4;
     *seg_rows = 0;
 }
@@ -134,8 +157,9 @@ int rdcnn_create(rdcnn_t *out, int rows, int cols, int bc, const rdcnn_params_t 
     if (!out) return fail(RDCNN_EINVAL, "rdcnn_create: out is NULL");
     *out = nullptr;
     if (rows < 1 || cols < 1) return fail(RDCNN_EINVAL, "rdcnn_create: grid %dx%d", rows, cols);
-    if ((long long)rows * cols > (1LL << 40))
-        return fail(RDCNN_EINVAL, "rdcnn_create: grid too large");
+    if ((long long)rows * cols >= (1LL << 30))
+        return fail(RDCNN_EINVAL, "rdcnn_create: grid of %lld cells; at most 2^30-1 (one plane "
+                    "must stay below 4 GiB)", (long long)rows * cols);
     if (bc != RDCNN_BC_PERIODIC && bc != RDCNN_BC_ZEROFLUX)
         return fail(RDCNN_EINVAL, "rdcnn_create: unknown boundary rule %d", bc);
     if (!p || !finite_params(p)) return fail(RDCNN_EINVAL, "rdcnn_create: missing or non-finite parameters");
@@ -216,6 +240,12 @@ int rdcnn_adjoint(rdcnn_t h, const float *states_dev, long long S, float *adj_de
     if (S == 0) return RDCNN_OK;
     int cpl = h->adj_cpl, depth = h->adj_depth, seg = h->adj_seg_rows;
     if (depth == 0) adj_auto_config(h, &cpl, &depth, &seg);
+    {
+        // A pass reads its states through one 4 GiB buffer resource.
+        const long long cap = ((1LL << 32) - 1) / (8LL * h->R * h->C);
+        if (cap < 1) return fail(RDCNN_EINVAL, "rdcnn_adjoint: grid too large");
+        if (depth > cap) depth = (int)cap;
+    }
     // Every pass has `depth` steps except possibly the last; size the partial
     // buffer for the larger tiling of the two.
     rd::StreamGeom gfull, glast;

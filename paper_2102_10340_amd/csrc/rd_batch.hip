@@ -1,0 +1,410 @@
+// rd_batch.hip -- many RD-CNN grids of uneven size and parameters advanced
+// together (the paper's parameter-space exploration, Sec. III, run as one
+// batch instead of one simulation at a time).
+//
+// All instances live in two packed ping-pong buffers; instance i occupies
+// 2*R_i*C_i floats (u plane, v plane) at a 256-byte aligned offset.  One launch
+// advances every instance by K steps: its workgroups walk a flat tile list
+// that covers all instances (strips x segments of each grid, as in the single
+// grid kernel), each tile carrying its instance's offset, size and parameters,
+// sorted by decreasing work so the longest tiles start first.  A run of T steps
+// is ceil(T/K) such launches, optionally captured once into a HIP graph and
+// replayed.
+#include <math.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "rd_fwd_body.h"
+#include "rd_launch.h"
+#include "rdcnn.h"
+
+namespace rd {
+
+struct BatchInst {
+    long long off;  // float offset of the instance in a packed buffer
+    int R, C;
+    Gene g;
+};
+
+struct BatchTile {
+    int inst, x0, y0, y1;
+};
+
+struct BatchArgs {
+    const BatchTile *tiles;
+    const BatchInst *insts;
+    int ntiles;
+    const float *in;
+    float *out;
+    int bc, wout, kpad;
+};
+
+template <int CPL, int K>
+__global__ __launch_bounds__(64) void batch_step_kernel(BatchArgs B)
+{
+    const int id = blockIdx.x;
+    if (id >= B.ntiles) return;
+    const BatchTile bt = B.tiles[id];
+    const BatchInst in = B.insts[bt.inst];
+    StreamArgs A;
+    A.t.R = in.R;
+    A.t.C = in.C;
+    A.t.bc = B.bc;
+    A.t.wout = B.wout;
+    A.t.kpad = B.kpad;
+    A.t.h = 0;
+    A.t.nsegs = 0;
+    A.t.ntiles = 0;
+    A.t.per_xcd = 0;
+    A.t.vec_ok = (in.C % CPL) == 0;
+    A.in = B.in + in.off;
+    A.out = B.out + in.off;
+    A.g = in.g;
+    A.rec = nullptr;
+    Tile<CPL> t;
+    t.setup(A.t, id, bt.x0, bt.y0, bt.y1);
+    if (t.fast)
+        stream_body<CPL, K, false, true>(A, t);
+    else
+        stream_body<CPL, K, false, false>(A, t);
+}
+
+namespace {
+
+using BatchFn = void (*)(BatchArgs);
+
+template <int CPL, int... Ks>
+constexpr BatchFn pick(int k, std::integer_sequence<int, Ks...>)
+{
+    BatchFn f = nullptr;
+    ((f = (k == Ks + 1) ? &batch_step_kernel<CPL, Ks + 1> : f), ...);
+    return f;
+}
+
+}  // namespace
+
+hipError_t launch_batch(const BatchTile *tiles, const BatchInst *insts, int ntiles,
+                        const float *in, float *out, int bc, int cpl, int depth, hipStream_t s)
+{
+    BatchFn f = nullptr;
+    if (cpl == 4)
+        f = pick<4>(depth, std::make_integer_sequence<int, kMaxDepthCpl4>{});
+    else if (cpl == 2)
+        f = pick<2>(depth, std::make_integer_sequence<int, kMaxDepthCpl2>{});
+    if (!f || ntiles < 1) return hipErrorInvalidValue;
+    BatchArgs a;
+    a.tiles = tiles;
+    a.insts = insts;
+    a.ntiles = ntiles;
+    a.in = in;
+    a.out = out;
+    a.bc = bc;
+    a.kpad = (depth + cpl - 1) / cpl * cpl;
+    a.wout = 64 * cpl - 2 * a.kpad;
+    hipLaunchKernelGGL(f, dim3((unsigned)ntiles), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace rd
+
+// ---------------------------------------------------------------- C ABI
+
+struct TileTable {
+    int depth = 0;
+    int ntiles = 0;
+    rd::BatchTile *dev = nullptr;
+};
+
+struct rdcnn_batch {
+    int n, bc;
+    std::vector<int> R, C;
+    std::vector<long long> off;
+    std::vector<rd::Gene> g;
+    float *buf[2];
+    int cur;
+    hipStream_t stream;
+    int cpl, depth, seg_rows;  // forced settings, 0 = automatic
+    rd::BatchInst *insts_dev;
+    std::vector<TileTable> tables;
+    int use_graph;
+    hipGraphExec_t graph;
+    long long graph_T;
+    int graph_cur, graph_cpl, graph_depth, graph_seg;
+};
+
+#define bfail(...) rd::set_error(__VA_ARGS__)
+
+namespace {
+
+void free_tables(rdcnn_batch *b)
+{
+    for (TileTable &t : b->tables)
+        if (t.dev) (void)hipFree(t.dev);
+    b->tables.clear();
+}
+
+void drop_graph(rdcnn_batch *b)
+{
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    b->graph_T = -1;
+}
+
+void batch_config(const rdcnn_batch *b, int *cpl, int *depth, int *seg)
+{
+    *cpl = b->cpl ? b->cpl : 4;
+    *depth = b->depth ? b->depth : 8;
+    *seg = b->seg_rows ? b->seg_rows : 64;
+}
+
+// Tile list for one pass depth: every instance cut into strips of wout output
+// columns and segments of `seg` rows, longest tiles first.
+int table_for(rdcnn_batch *b, int cpl, int depth, int seg, const TileTable **out)
+{
+    for (const TileTable &t : b->tables)
+        if (t.depth == depth) {
+            *out = &t;
+            return RDCNN_OK;
+        }
+    const int kpad = (depth + cpl - 1) / cpl * cpl;
+    const int wout = 64 * cpl - 2 * kpad;
+    if (wout <= 0) return bfail(RDCNN_EINVAL, "batch: depth %d too large for cpl %d", depth, cpl);
+    std::vector<rd::BatchTile> tiles;
+    for (int i = 0; i < b->n; ++i) {
+        const int R = b->R[i], C = b->C[i];
+        const int h = seg < R ? seg : R;
+        for (int sx = 0; sx * wout < C; ++sx)
+            for (int y0 = 0; y0 < R; y0 += h) {
+                rd::BatchTile t;
+                t.inst = i;
+                t.x0 = sx * wout - kpad;
+                t.y0 = y0;
+                t.y1 = y0 + h < R ? y0 + h : R;
+                tiles.push_back(t);
+            }
+    }
+    if (tiles.size() >= (1u << 31)) return bfail(RDCNN_EINVAL, "batch: too many tiles");
+    std::stable_sort(tiles.begin(), tiles.end(), [](const rd::BatchTile &a, const rd::BatchTile &c) {
+        return (a.y1 - a.y0) > (c.y1 - c.y0);
+    });
+    TileTable t;
+    t.depth = depth;
+    t.ntiles = (int)tiles.size();
+    hipError_t e = hipMalloc((void **)&t.dev, sizeof(rd::BatchTile) * tiles.size());
+    if (e != hipSuccess) return bfail(RDCNN_ENOMEM, "batch: tile table: %s", hipGetErrorString(e));
+    e = hipMemcpy(t.dev, tiles.data(), sizeof(rd::BatchTile) * tiles.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(t.dev);
+        return bfail(RDCNN_EHIP, "batch: tile table upload: %s", hipGetErrorString(e));
+    }
+    b->tables.push_back(t);
+    *out = &b->tables.back();
+    return RDCNN_OK;
+}
+
+// Enqueue the launches of T steps; cur flips once per launch.
+int enqueue_steps(rdcnn_batch *b, long long T, int cpl, int depth, int seg)
+{
+    while (T > 0) {
+        const int k = (int)(T < depth ? T : depth);
+        const TileTable *t = nullptr;
+        for (const TileTable &x : b->tables)
+            if (x.depth == k) t = &x;
+        if (!t) return bfail(RDCNN_ESTATE, "batch: missing tile table for depth %d", k);
+        hipError_t e = rd::launch_batch(t->dev, b->insts_dev, t->ntiles, b->buf[b->cur],
+                                        b->buf[1 - b->cur], b->bc, cpl, k, b->stream);
+        if (e != hipSuccess) return bfail(RDCNN_EHIP, "batch: launch: %s", hipGetErrorString(e));
+        b->cur = 1 - b->cur;
+        T -= k;
+    }
+    return RDCNN_OK;
+}
+
+bool finite_gene(const rdcnn_params_t &p)
+{
+    const float v[8] = {p.dt, p.a, p.b, p.eps, p.c, p.k3, p.Du, p.Dv};
+    for (float x : v)
+        if (!isfinite(x)) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rdcnn_batch_create(rdcnn_batch_t *out, int n, const int *rows, const int *cols,
+                       const long long *offsets, const rdcnn_params_t *params, int bc,
+                       const float *x_dev, const long long *x_offsets, float ka, float *buf0_dev,
+                       float *buf1_dev, long long buf_floats, void *stream)
+{
+    if (!out) return bfail(RDCNN_EINVAL, "rdcnn_batch_create: out is NULL");
+    *out = nullptr;
+    if (n < 1 || !rows || !cols || !offsets || !params || !x_dev || !x_offsets || !buf0_dev ||
+        !buf1_dev)
+        return bfail(RDCNN_EINVAL, "rdcnn_batch_create: NULL argument or n < 1");
+    if (bc != RDCNN_BC_PERIODIC && bc != RDCNN_BC_ZEROFLUX)
+        return bfail(RDCNN_EINVAL, "rdcnn_batch_create: unknown boundary rule %d", bc);
+    if (buf0_dev == buf1_dev) return bfail(RDCNN_EINVAL, "rdcnn_batch_create: buffers alias");
+    if (!isfinite(ka)) return bfail(RDCNN_EINVAL, "rdcnn_batch_create: non-finite ka");
+    // Instances must be aligned, inside the buffers and pairwise disjoint.
+    std::vector<std::pair<long long, long long>> span(n);
+    for (int i = 0; i < n; ++i) {
+        if (rows[i] < 1 || cols[i] < 1 || (long long)rows[i] * cols[i] >= (1LL << 30))
+            return bfail(RDCNN_EINVAL, "rdcnn_batch_create: instance %d has size %dx%d", i, rows[i],
+                         cols[i]);
+        if (offsets[i] < 0 || offsets[i] % 64 != 0)
+            return bfail(RDCNN_EINVAL, "rdcnn_batch_create: offset of instance %d not a multiple "
+                         "of 64 floats", i);
+        const long long len = 2LL * rows[i] * cols[i];
+        if (offsets[i] + len > buf_floats)
+            return bfail(RDCNN_EINVAL, "rdcnn_batch_create: instance %d runs past the buffer", i);
+        if (x_offsets[i] < 0) return bfail(RDCNN_EINVAL, "rdcnn_batch_create: bad x offset %d", i);
+        if (!finite_gene(params[i]))
+            return bfail(RDCNN_EINVAL, "rdcnn_batch_create: non-finite parameter (instance %d)", i);
+        span[i] = {offsets[i], offsets[i] + len};
+    }
+    std::sort(span.begin(), span.end());
+    for (int i = 1; i < n; ++i)
+        if (span[i].first < span[i - 1].second)
+            return bfail(RDCNN_EINVAL, "rdcnn_batch_create: instances overlap");
+    rdcnn_batch *b = new (std::nothrow) rdcnn_batch;
+    if (!b) return bfail(RDCNN_ENOMEM, "rdcnn_batch_create: out of host memory");
+    b->n = n;
+    b->bc = bc;
+    b->R.assign(rows, rows + n);
+    b->C.assign(cols, cols + n);
+    b->off.assign(offsets, offsets + n);
+    b->g.resize(n);
+    std::vector<rd::BatchInst> inst(n);
+    for (int i = 0; i < n; ++i) {
+        const rdcnn_params_t &p = params[i];
+        rd::Gene g{p.dt, p.a, p.b, p.eps, p.c, p.k3, p.Du, p.Dv};
+        b->g[i] = g;
+        inst[i].off = offsets[i];
+        inst[i].R = rows[i];
+        inst[i].C = cols[i];
+        inst[i].g = g;
+    }
+    b->buf[0] = buf0_dev;
+    b->buf[1] = buf1_dev;
+    b->cur = 0;
+    b->stream = (hipStream_t)stream;
+    b->cpl = b->depth = b->seg_rows = 0;
+    b->insts_dev = nullptr;
+    b->use_graph = 0;
+    b->graph = nullptr;
+    b->graph_T = -1;
+    b->graph_cur = b->graph_cpl = b->graph_depth = b->graph_seg = 0;
+    hipError_t e = hipMalloc((void **)&b->insts_dev, sizeof(rd::BatchInst) * n);
+    if (e != hipSuccess) {
+        delete b;
+        return bfail(RDCNN_ENOMEM, "rdcnn_batch_create: instance table: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpy(b->insts_dev, inst.data(), sizeof(rd::BatchInst) * n, hipMemcpyHostToDevice);
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+        e = rd::launch_init(x_dev + x_offsets[i], ka, buf0_dev + offsets[i],
+                            (long long)rows[i] * cols[i], b->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(b->insts_dev);
+        delete b;
+        return bfail(RDCNN_EHIP, "rdcnn_batch_create: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return RDCNN_OK;
+}
+
+int rdcnn_batch_set_kernel(rdcnn_batch_t b, int depth, int cols_per_lane, int seg_rows)
+{
+    if (!b) return bfail(RDCNN_EINVAL, "rdcnn_batch_set_kernel: NULL handle");
+    if (depth == 0 && cols_per_lane == 0 && seg_rows == 0) {
+        b->cpl = b->depth = b->seg_rows = 0;
+    } else {
+        if (cols_per_lane != 2 && cols_per_lane != 4)
+            return bfail(RDCNN_EINVAL, "rdcnn_batch_set_kernel: cols_per_lane %d", cols_per_lane);
+        if (depth < 1 || depth > rd::max_depth(cols_per_lane))
+            return bfail(RDCNN_EINVAL, "rdcnn_batch_set_kernel: depth %d", depth);
+        if (seg_rows < 0) return bfail(RDCNN_EINVAL, "rdcnn_batch_set_kernel: seg_rows < 0");
+        b->cpl = cols_per_lane;
+        b->depth = depth;
+        b->seg_rows = seg_rows;
+    }
+    free_tables(b);
+    drop_graph(b);
+    return RDCNN_OK;
+}
+
+int rdcnn_batch_use_graph(rdcnn_batch_t b, int on)
+{
+    if (!b) return bfail(RDCNN_EINVAL, "rdcnn_batch_use_graph: NULL handle");
+    b->use_graph = on ? 1 : 0;
+    if (!on) drop_graph(b);
+    return RDCNN_OK;
+}
+
+int rdcnn_batch_step(rdcnn_batch_t b, long long T)
+{
+    if (!b) return bfail(RDCNN_EINVAL, "rdcnn_batch_step: NULL handle");
+    if (T < 0) return bfail(RDCNN_EINVAL, "rdcnn_batch_step: T < 0");
+    if (T == 0) return RDCNN_OK;
+    int cpl, depth, seg;
+    batch_config(b, &cpl, &depth, &seg);
+    const TileTable *t;
+    int rc = table_for(b, cpl, depth, seg, &t);
+    if (rc == RDCNN_OK && T % depth) rc = table_for(b, cpl, (int)(T % depth), seg, &t);
+    if (rc != RDCNN_OK) return rc;
+    const long long passes = (T + depth - 1) / depth;
+    if (!b->use_graph) return enqueue_steps(b, T, cpl, depth, seg);
+    if (!b->stream) return bfail(RDCNN_EINVAL, "batch: graph capture needs a non-default stream");
+    if (!(b->graph && b->graph_T == T && b->graph_cur == b->cur && b->graph_cpl == cpl &&
+          b->graph_depth == depth && b->graph_seg == seg)) {
+        drop_graph(b);
+        const int cur0 = b->cur;
+        hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) return bfail(RDCNN_EHIP, "batch: begin capture: %s", hipGetErrorString(e));
+        rc = enqueue_steps(b, T, cpl, depth, seg);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->stream, &g);
+        b->cur = cur0;
+        if (rc != RDCNN_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return bfail(RDCNN_EHIP, "batch: end capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            b->graph = nullptr;
+            return bfail(RDCNN_EHIP, "batch: instantiate: %s", hipGetErrorString(e));
+        }
+        b->graph_T = T;
+        b->graph_cur = cur0;
+        b->graph_cpl = cpl;
+        b->graph_depth = depth;
+        b->graph_seg = seg;
+    }
+    hipError_t e = hipGraphLaunch(b->graph, b->stream);
+    if (e != hipSuccess) return bfail(RDCNN_EHIP, "batch: graph launch: %s", hipGetErrorString(e));
+    if (passes % 2) b->cur = 1 - b->cur;
+    return RDCNN_OK;
+}
+
+int rdcnn_batch_current(rdcnn_batch_t b, float **state_dev)
+{
+    if (!b || !state_dev) return bfail(RDCNN_EINVAL, "rdcnn_batch_current: NULL argument");
+    *state_dev = b->buf[b->cur];
+    return RDCNN_OK;
+}
+
+int rdcnn_batch_destroy(rdcnn_batch_t b)
+{
+    if (!b) return RDCNN_OK;
+    drop_graph(b);
+    free_tables(b);
+    if (b->insts_dev) (void)hipFree(b->insts_dev);
+    delete b;
+    return RDCNN_OK;
+}
+
+}  // extern "C"

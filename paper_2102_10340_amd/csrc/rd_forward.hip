@@ -18,8 +18,8 @@
 //                       valid region shrinks by one cell per level), read from
 //                       the boundary-extended grid (map_index), so the boundary
 //                       rule costs nothing inside the loop.
+#include "rd_fwd_body.h"
 #include "rd_launch.h"
-#include "rd_stream.h"
 
 namespace rd {
 
@@ -84,113 +84,15 @@ hipError_t launch_naive(const float *in, float *out, int R, int C, int bc, const
 
 // ---------------------------------------------------------------- streamed
 
-struct StreamArgs {
-    TileArgs t;
-    const float *in;
-    float *out;
-    Gene g;
-    float *rec;          // recording: state q0+j of the pass goes to rec + (q0+j)*stride
-    long long rec_q0;
-    long long rec_stride;
-};
-
 template <int CPL, int K, bool REC>
 __global__ __launch_bounds__(64) void stream_step_kernel(StreamArgs A)
 {
     Tile<CPL> t;
     if (!t.init(A.t)) return;
-    const int C = A.t.C, R = A.t.R, bc = A.t.bc;
-    const size_t plane = (size_t)R * C;
-    const float *__restrict__ iu = A.in;
-    const float *__restrict__ iv = A.in + plane;
-    float *__restrict__ ou = A.out;
-    float *__restrict__ ov = A.out + plane;
-    const Gene g = A.g;
-    const int y0 = t.y0, y1 = t.y1;
-
-    const int rbase = y0 - K;                     // first row read (level 0)
-    const int n_real = y1 - y0 + 2 * K;           // rows walked
-    const int n_iter = (n_real + 2) / 3 * 3;      // ... padded to a multiple of 3
-
-    // Row q (counted from rbase) of time level j lives in slot q % 3 of level
-    // j.  Iteration `it` reads level-0 row it and makes level-(j+1) row it-j-1
-    // from level-j rows it-j-2, it-j-1, it-j; the new row overwrites the slot of
-    // level-(j+1) row it-j-4, which nothing needs any more.  With the loop
-    // unrolled three times every slot index is a compile-time constant, so the
-    // window rotates without register copies.
-    float bu[K][3][CPL], bv[K][3][CPL];
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-#pragma unroll
-            for (int e = 0; e < CPL; ++e) bu[j][q][e] = bv[j][q][e] = 0.0f;
-    {
-        const int rr = map_index(rbase, R, bc);
-        load_row<CPL>(iu, rr, C, t, bu[0][0]);
-        load_row<CPL>(iv, rr, C, t, bv[0][0]);
-    }
-
-    auto iteration = [&](const int it, const int S) __attribute__((always_inline)) {
-        float tu[CPL], tv[CPL];  // row it-K of level K (the pass output)
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const Slots sl(S, j);
-            float *du = j + 1 < K ? bu[j + 1][sl.cs] : tu;  // level j+1, row it-j-1
-            float *dv = j + 1 < K ? bv[j + 1][sl.cs] : tv;
-            // Level j+1 has all three input rows from it = 2j+2 on; rows made
-            // after it = n_real are beyond the segment's cone.
-            if (it >= 2 * j + 2 && it < n_real) {
-                const float lu = from_left_lane(bu[j][sl.cs][CPL - 1]);
-                const float ru = from_right_lane(bu[j][sl.cs][0]);
-                const float lv = from_left_lane(bv[j][sl.cs][CPL - 1]);
-                const float rv = from_right_lane(bv[j][sl.cs][0]);
-#pragma unroll
-                for (int e = 0; e < CPL; ++e) {
-                    const float uW = e == 0 ? lu : bu[j][sl.cs][e - 1];
-                    const float uE = e == CPL - 1 ? ru : bu[j][sl.cs][e + 1];
-                    const float vW = e == 0 ? lv : bv[j][sl.cs][e - 1];
-                    const float vE = e == CPL - 1 ? rv : bv[j][sl.cs][e + 1];
-                    cell_update(g, bu[j][sl.cs][e], bv[j][sl.cs][e], bu[j][sl.ps][e],
-                                bu[j][sl.ns][e], uW, uE, bv[j][sl.ps][e], bv[j][sl.ns][e], vW, vE,
-                                du[e], dv[e]);
-                }
-                if (REC && j + 1 < K) {
-                    const int m = rbase + it - j - 1;
-                    if (m >= y0 && m < y1) {
-                        float *r = A.rec + (A.rec_q0 + j + 1) * A.rec_stride;
-                        store_row<CPL>(r, m, C, t, bu[j + 1][sl.cs]);
-                        store_row<CPL>(r + plane, m, C, t, bv[j + 1][sl.cs]);
-                    }
-                }
-            }
-            if (j == 0) {
-                if (REC) {
-                    const int m = rbase + it;  // level-0 row it
-                    if (m >= y0 && m < y1) {
-                        float *r = A.rec + A.rec_q0 * A.rec_stride;
-                        store_row<CPL>(r, m, C, t, bu[0][sl.ns]);
-                        store_row<CPL>(r + plane, m, C, t, bv[0][sl.ns]);
-                    }
-                }
-                // Level-0 row it-2 is spent: fetch row it+1 into its slot.
-                const int rr = map_index(rbase + it + 1, R, bc);
-                load_row<CPL>(iu, rr, C, t, bu[0][sl.ps]);
-                load_row<CPL>(iv, rr, C, t, bv[0][sl.ps]);
-            }
-        }
-        const int m = rbase + it - K;  // row of level K now in (tu, tv)
-        if (m >= y0 && m < y1) {
-            store_row<CPL>(ou, m, C, t, tu);
-            store_row<CPL>(ov, m, C, t, tv);
-        }
-    };
-
-    for (int it = 0; it < n_iter; it += 3) {
-        iteration(it, 0);
-        iteration(it + 1, 1);
-        iteration(it + 2, 2);
-    }
+    if (t.fast)
+        stream_body<CPL, K, REC, true>(A, t);
+    else
+        stream_body<CPL, K, REC, false>(A, t);
 }
 
 bool stream_geometry(int R, int C, int cpl, int depth, int seg_rows, StreamGeom *g)
@@ -270,9 +172,7 @@ hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, cons
     a.in = in;
     a.out = out;
     a.g = g;
-    a.rec = rec;
-    a.rec_q0 = rec_q0;
-    a.rec_stride = 2LL * R * C;
+    a.rec = rec ? rec + rec_q0 * 2LL * R * C : nullptr;
     hipLaunchKernelGGL(f, dim3((unsigned)(8 * geom.per_xcd)), dim3(64), 0, s, a);
     return hipGetLastError();
 }

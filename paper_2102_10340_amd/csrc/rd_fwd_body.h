@@ -1,0 +1,121 @@
+// rd_fwd_body.h -- the register-streamed forward pass over one tile, shared by
+// the single-grid kernel (rd_forward.hip) and the batched kernel (rd_batch.hip).
+//
+// K Euler steps of Eq. (1)-(3) (arXiv 2102.10340, Sec. II.A) per pass over HBM.
+// One 64-lane wavefront owns a strip of 64*CPL columns and a segment of output
+// rows; it walks down the rows once, keeping three rows of (u, v) per time level
+// in registers (see the slot scheme below).  East/west neighbours across lanes
+// come from DPP wave shifts, north/south ones from the register window.
+#pragma once
+
+#include "rd_stream.h"
+
+namespace rd {
+
+struct StreamArgs {
+    TileArgs t;
+    const float *in;
+    float *out;
+    Gene g;
+    float *rec;  // recording: level j of the pass goes to state j of rec (null: off)
+};
+
+template <int CPL, int K, bool REC, bool FAST>
+__device__ __forceinline__ void stream_body(const StreamArgs &A, const Tile<CPL> &t)
+{
+    const int C = A.t.C, R = A.t.R, bc = A.t.bc;
+    const unsigned pbytes = 4u * (unsigned)R * (unsigned)C;  // one plane
+    const Buf iu(A.in, pbytes), iv(A.in + (size_t)R * C, pbytes);
+    const Buf ou(A.out, pbytes), ov(A.out + (size_t)R * C, pbytes);
+    // K recorded states, u plane then v plane each: state j at byte 2*j*pbytes.
+    const Buf rb(REC ? A.rec : A.in, REC ? 2u * (unsigned)K * pbytes : 0u);
+    const Gene g = A.g;
+    const int y0 = t.y0, y1 = t.y1;
+
+    const int rbase = y0 - K;                 // first row read (level 0)
+    const int n_real = y1 - y0 + 2 * K;       // rows walked
+    const int n_iter = (n_real + 2) / 3 * 3;  // ... padded to a multiple of 3
+
+    // Row q (counted from rbase) of time level j lives in slot q % 3 of level
+    // j.  Iteration `it` reads level-0 row it and makes level-(j+1) row it-j-1
+    // from level-j rows it-j-2, it-j-1, it-j; the new row overwrites the slot of
+    // level-(j+1) row it-j-4, which nothing needs any more.  With the loop
+    // unrolled three times every slot index is a compile-time constant, so the
+    // window rotates without register copies.
+    float bu[K][3][CPL], bv[K][3][CPL];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) bu[j][q][e] = bv[j][q][e] = 0.0f;
+    {
+        const unsigned ro = row_off(rbase, R, C, bc);
+        load_row<CPL, FAST>(iu, ro, t, bu[0][0]);
+        load_row<CPL, FAST>(iv, ro, t, bv[0][0]);
+    }
+
+    auto iteration = [&](const int it, const int S) __attribute__((always_inline)) {
+        float tu[CPL], tv[CPL];  // row it-K of level K (the pass output)
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const Slots sl(S, j);
+            float *du = j + 1 < K ? bu[j + 1][sl.cs] : tu;  // level j+1, row it-j-1
+            float *dv = j + 1 < K ? bv[j + 1][sl.cs] : tv;
+            // Level j+1 has all three input rows from it = 2j+2 on; rows made
+            // after it = n_real are beyond the segment's cone.
+            if (it >= 2 * j + 2 && it < n_real) {
+                const float lu = from_left_lane(bu[j][sl.cs][CPL - 1]);
+                const float ru = from_right_lane(bu[j][sl.cs][0]);
+                const float lv = from_left_lane(bv[j][sl.cs][CPL - 1]);
+                const float rv = from_right_lane(bv[j][sl.cs][0]);
+#pragma unroll
+                for (int e = 0; e < CPL; ++e) {
+                    const float uW = e == 0 ? lu : bu[j][sl.cs][e - 1];
+                    const float uE = e == CPL - 1 ? ru : bu[j][sl.cs][e + 1];
+                    const float vW = e == 0 ? lv : bv[j][sl.cs][e - 1];
+                    const float vE = e == CPL - 1 ? rv : bv[j][sl.cs][e + 1];
+                    cell_update(g, bu[j][sl.cs][e], bv[j][sl.cs][e], bu[j][sl.ps][e],
+                                bu[j][sl.ns][e], uW, uE, bv[j][sl.ps][e], bv[j][sl.ns][e], vW, vE,
+                                du[e], dv[e]);
+                }
+                if (REC && j + 1 < K) {
+                    const int m = rbase + it - j - 1;
+                    if (m >= y0 && m < y1) {
+                        const unsigned o = 2u * (unsigned)(j + 1) * pbytes + 4u * (unsigned)m * C;
+                        store_row<CPL, FAST>(rb, o, C, t, bu[j + 1][sl.cs]);
+                        store_row<CPL, FAST>(rb, o + pbytes, C, t, bv[j + 1][sl.cs]);
+                    }
+                }
+            }
+            if (j == 0) {
+                if (REC) {
+                    const int m = rbase + it;  // level-0 row it
+                    if (m >= y0 && m < y1) {
+                        const unsigned o = 4u * (unsigned)m * C;
+                        store_row<CPL, FAST>(rb, o, C, t, bu[0][sl.ns]);
+                        store_row<CPL, FAST>(rb, o + pbytes, C, t, bv[0][sl.ns]);
+                    }
+                }
+                // Level-0 row it-2 is spent: fetch row it+1 into its slot.
+                const unsigned ro = row_off(rbase + it + 1, R, C, bc);
+                load_row<CPL, FAST>(iu, ro, t, bu[0][sl.ps]);
+                load_row<CPL, FAST>(iv, ro, t, bv[0][sl.ps]);
+            }
+        }
+        const int m = rbase + it - K;  // row of level K now in (tu, tv)
+        if (m >= y0 && m < y1) {
+            const unsigned o = 4u * (unsigned)m * C;
+            store_row<CPL, FAST>(ou, o, C, t, tu);
+            store_row<CPL, FAST>(ov, o, C, t, tv);
+        }
+    };
+
+    for (int it = 0; it < n_iter; it += 3) {
+        iteration(it, 0);
+        iteration(it + 1, 1);
+        iteration(it + 2, 2);
+    }
+}
+
+}  // namespace rd

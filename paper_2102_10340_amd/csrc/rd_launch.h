@@ -6,6 +6,9 @@
 
 namespace rd {
 
+// Record a message for rdcnn_last_error() (thread-local) and return `code`.
+int set_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
 // Largest number of time steps one register-streamed pass may take, per
 // columns-per-lane setting (bounded by the 256 architected VGPRs a wave has).
 constexpr int kMaxDepthCpl2 = 16;
@@ -67,6 +70,12 @@ hipError_t launch_zero(double *p, long long n, hipStream_t s);
 // Fold ntiles rows of partial sums into the eight gradients, added to dtheta.
 hipError_t launch_adjoint_finish(const double *partial, int ntiles, const Gene &g,
                                  double *dtheta, hipStream_t s);
+
+// One launch of the batched kernel: `depth` steps for every tile of the list.
+struct BatchTile;
+struct BatchInst;
+hipError_t launch_batch(const BatchTile *tiles, const BatchInst *insts, int ntiles,
+                        const float *in, float *out, int bc, int cpl, int depth, hipStream_t s);
 
 // gx = ka (lam + mu) over n cells.
 hipError_t launch_init_backward(const float *adj, long long n, float ka, float *gx,

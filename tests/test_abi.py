@@ -49,7 +49,7 @@ def test_create_rejects_bad_arguments(L):
     fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
     cases = [
         dict(rows=0), dict(cols=-3), dict(bc=7), dict(x=None), dict(b0=None),
-        dict(b1=fake.value + 0), dict(ka=float("nan")),
+        dict(b1=fake.value + 0), dict(ka=float("nan")), dict(rows=1 << 15, cols=1 << 15),
     ]
     for c in cases:
         args = dict(rows=4, cols=4, bc=1, x=0x2000, ka=1.0, b0=0x3000, b1=0x4000)

@@ -131,7 +131,7 @@ def test_autograd_function_matches_oracle(bc):
     z = rng.standard_normal((R, C)).astype(np.float32)
     xt = torch.from_numpy(x).cuda().requires_grad_(True)
     theta = torch.tensor([g[k] for k in KEYS], dtype=torch.float64, requires_grad=True)
-    for S in (0, 1, 7, 150):
+    for S in (0, -1, 1, 7, 150):
         xt.grad = None
         theta.grad = None
         u, v = simulate(xt, theta, T, bc, 1.0, S)
