@@ -47,6 +47,8 @@ def parse():
                     help="time steps per benchmark step (profiler runs use fewer)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="first run a plain device copy of this size (scales HBM counters)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the differentiation and parameter-sweep workloads")
     return ap.parse_args()
 
 
@@ -66,6 +68,98 @@ def measured_traffic(kernel_prefix: str):
                 return None
         return rec["traffic_bytes_per_launch"]
     return None
+
+
+def _timed(fn, stream):
+    """Seconds for fn() between HIP events on `stream`, synchronized on both sides."""
+    import torch
+    stream.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    stream.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def bench_fwd_bwd(stream):
+    """Differentiation workload: 1024x1024, T = 2000, plain gene, x ~ U[-1,1]
+    (seed 0), loss = MSE(u_T, three-sinusoid stripe target); gradients with
+    respect to x and all eight parameters."""
+    import torch
+    from paper_2102_10340_amd import Simulation, simulate
+    N, T = 1024, 2000
+    g = W.PLAIN_GENE
+    keys = ("dt", "a", "b", "eps", "c", "k3", "Du", "Dv")
+    x = torch.from_numpy(W.uniform_x(N, N, 0)).cuda()
+    target = torch.from_numpy(W.stripe_target(N, N, 0)).cuda()
+
+    def fwd():
+        sim = Simulation(x, g, "zeroflux")
+        sim.step(T)
+        sim.read()
+        sim.close()
+
+    def fwd_bwd(grads):
+        xt = x.clone().requires_grad_(True)
+        theta = torch.tensor([g[k] for k in keys], dtype=torch.float64, requires_grad=True)
+        u, _ = simulate(xt, theta, T, "zeroflux", grads=grads)
+        ((u - target) ** 2).mean().backward()
+
+    sub = ("Du", "Dv", "eps")
+    fwd()
+    fwd_bwd(sub)
+    fwd_bwd(None)
+    tf = min(_timed(fwd, stream) for _ in range(3))
+    tfb = min(_timed(lambda: fwd_bwd(sub), stream) for _ in range(3))
+    tfb8 = min(_timed(lambda: fwd_bwd(None), stream) for _ in range(3))
+    cells = N * N * T
+    return {"workload": "1024x1024 zero-flux, T=2000, MSE to stripe target, grads wrt x, Du, Dv "
+                        "and eps; whole trajectory recorded in HBM",
+            "fwd_gcells": cells / tf / 1e9, "fwd_bwd_gcells": cells / tfb / 1e9,
+            "fwd_ms": tf * 1e3, "fwd_bwd_ms": tfb * 1e3, "ratio_fwd_bwd_to_fwd": tfb / tf,
+            "fwd_bwd_all8_ms": tfb8 * 1e3, "ratio_all8_to_fwd": tfb8 / tf}
+
+
+def bench_batched(stream, per_class=4):
+    """Parameter sweep: 1024 instances, side uniform over {128,256,512,1024},
+    Du ~ U[0.01,0.2], Dv ~ U[0.2,1], epsilon ~ U[0.02,0.2], zero-flux, x ~ U[-1,1]
+    per instance, T = 5000, one graph launch.  Baseline: the same instances run
+    one at a time (rdcnn_step(T) on one stream, default pass settings), timed on
+    `per_class` instances of each size and scaled by the class counts.  Both
+    sides are timed on steps T..2T (after an untimed first T steps, which also
+    captures the batch's graph), and the sampled instances are compared bit for
+    bit between the two."""
+    import torch
+    from paper_2102_10340_amd import Batch, Simulation
+    T = 5000
+    inst = W.sweep_instances(1024, 0)
+    xs = [torch.from_numpy(W.uniform_x(d["rows"], d["cols"], d["seed"])).cuda() for d in inst]
+    b = Batch(xs, [d["gene"] for d in inst], "zeroflux")
+    b.use_graph(True)
+    b.step(T)  # captures the T-step graph and runs it once (untimed)
+    tb = _timed(lambda: b.step(T), stream)  # graph replay: steps T..2T
+    cells = sum(d["rows"] * d["cols"] for d in inst)
+    # per-instance baseline on a sample of each size class
+    t_single, same = 0.0, True
+    for side in (128, 256, 512, 1024):
+        idx = [i for i, d in enumerate(inst) if d["rows"] == side]
+        ts = []
+        for i in idx[:per_class]:
+            sim = Simulation(xs[i], inst[i]["gene"], "zeroflux")
+            sim.step(T)
+            ts.append(_timed(lambda: sim.step(T), stream))
+            same &= bool(torch.equal(sim.state(), b.state(i)))
+            sim.close()
+        t_single += sum(ts) / len(ts) * len(idx)
+    b.close()
+    return {"workload": "1024 instances, sides {128,256,512,1024}, per-instance Du/Dv/eps, "
+                        "zero-flux, T=5000, one graph launch",
+            "batched_gcells": cells * T / tb / 1e9, "batched_s": tb,
+            "per_instance_gcells": cells * T / t_single / 1e9, "per_instance_s_est": t_single,
+            "speedup_vs_per_instance": t_single / tb, "sampled_instances_bitwise_equal": same,
+            "baseline_sample": f"{per_class} instances per size class, scaled by class counts"}
 
 
 def cpu_baseline(budget_s: float):
@@ -173,6 +267,11 @@ def main():
         "final_max_abs_u": alive,
     }
     sim.close()
+    if not args.no_extra:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            out["fwd_bwd"] = bench_fwd_bwd(stream)
+            out["batched"] = bench_batched(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -120,7 +120,7 @@ int rdcnn_current(rdcnn_t h, float **state_dev);
  * tuning; the default is chosen per grid shape).
  *   kind 0: automatic; 1: one thread per cell, one launch per step (reference
  *   kernel); 2: register-streamed kernel doing up to `depth` steps per HBM pass.
- *   cols_per_lane 2 (depth 1..16) or 4 (depth 1..12); seg_rows: output rows
+ *   cols_per_lane 1 or 2 (depth 1..16) or 4 (depth 1..12); seg_rows: output rows
  *   per wavefront, 0 = automatic.  Other fields are ignored for kinds 0 and 1.
  *   Every setting gives bit-identical states.  Errors: RDCNN_EINVAL.
  */
@@ -145,7 +145,9 @@ int rdcnn_step_record(rdcnn_t h, long long T, float *states_dev);
  *               steps, on exit (dJ/du, dJ/dv) before them
  *   adj_tmp_dev scratch of the same size (contents overwritten)
  *   dtheta_dev  8 device doubles; dJ/dp of these S steps is ADDED, in the order
- *               dt, a, b, eps, c, k3, Du, Dv (rdcnn_params_t order)
+ *               dt, a, b, eps, c, k3, Du, Dv (rdcnn_params_t order), for the
+ *               parameters of the gradient mask (rdcnn_set_grad_mask; default
+ *               all), NaN for the others
  * Uses the handle's current parameters, boundary rule and stream.  S == 0 does
  * nothing.  The first call on a handle allocates a small device workspace for
  * per-tile partial sums (8 doubles per tile; freed by rdcnn_destroy).  Results
@@ -157,11 +159,20 @@ int rdcnn_adjoint(rdcnn_t h, const float *states_dev, long long S, float *adj_de
 
 /*
  * rdcnn_set_adjoint_kernel -- pass settings for rdcnn_adjoint: `depth` reverse
- * steps per HBM pass, cols_per_lane 2 (depth 1..8) or 4 (depth 1..6), seg_rows
+ * steps per HBM pass, cols_per_lane 1 or 2 (depth 1..8) or 4 (depth 1..6), seg_rows
  * output rows per wavefront (0 = automatic).  depth = cols_per_lane = 0 restores
  * the automatic choice.  Errors: RDCNN_EINVAL.
  */
 int rdcnn_set_adjoint_kernel(rdcnn_t h, int depth, int cols_per_lane, int seg_rows);
+
+/*
+ * rdcnn_set_grad_mask -- which parameter gradients later rdcnn_adjoint calls
+ * form: bit q set = parameter q in rdcnn_params_t order (dt = bit 0 ... Dv =
+ * bit 7); default 0xFF (all).  Entries outside the mask are set to NaN in
+ * dtheta_dev instead of being accumulated.  Leaving dt, c and k3 out skips three
+ * of the eight inner products.  mask must be in 1..0xFF.  Errors: RDCNN_EINVAL.
+ */
+int rdcnn_set_grad_mask(rdcnn_t h, unsigned mask);
 
 /*
  * rdcnn_init_backward -- chain rule through Eq. (1)'s first line (u = v = k_a x):
@@ -208,7 +219,7 @@ int rdcnn_batch_step(rdcnn_batch_t b, long long T);
 int rdcnn_batch_current(rdcnn_batch_t b, float **state_dev);
 
 /*
- * rdcnn_batch_set_kernel -- steps per pass (depth), cols_per_lane (2 or 4) and
+ * rdcnn_batch_set_kernel -- steps per pass (depth), cols_per_lane (1, 2 or 4) and
  * rows per tile (seg_rows, 0 = default) of later steps; all zero restores the
  * defaults.  Results are bit-identical for every setting.  Errors: RDCNN_EINVAL.
  */

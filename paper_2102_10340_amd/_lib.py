@@ -55,6 +55,7 @@ _SIGS = {
     "rdcnn_adjoint": [_P, _P, _LL, _P, _P, _P],
     "rdcnn_set_adjoint_kernel": [_P, _I, _I, _I],
     "rdcnn_init_backward": [_P, _LL, _F, _P, _P],
+    "rdcnn_set_grad_mask": [_P, ctypes.c_uint],
     "rdcnn_batch_create": [_PP, _I, _P, _P, _P, _P, _I, _P, _P, _F, _P, _P, _LL, _P],
     "rdcnn_batch_step": [_P, _LL],
     "rdcnn_batch_current": [_P, _PP],

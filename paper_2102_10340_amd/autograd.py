@@ -50,6 +50,16 @@ def choose_schedule(T: int, rows: int, cols: int, S: int, device) -> int:
     return default_segment(T, rows, cols)
 
 
+def grad_mask(grads) -> int:
+    """Bit mask for the parameters named in `grads` (None or "all": all eight)."""
+    if grads is None or grads == "all":
+        return 0xFF
+    m = 0
+    for name in grads:
+        m |= 1 << PARAM_FIELDS.index(name)
+    return m
+
+
 def _gene(theta: torch.Tensor):
     vals = theta.detach().to("cpu", torch.float64).tolist()
     if len(vals) != 8:
@@ -72,7 +82,8 @@ def _forward(sim: Simulation, T: int, S: int, dev):
     return u, v, ckpt, nseg
 
 
-def _backward(sim: Simulation, ckpt, nseg: int, T: int, S: int, gu, gv, dev, kernel=None):
+def _backward(sim: Simulation, ckpt, nseg: int, T: int, S: int, gu, gv, dev, kernel=None,
+              mask: int = 0xFF):
     R, C = sim.rows, sim.cols
     adj = torch.empty((2, R, C), dtype=torch.float32, device=dev)
     adj[0].copy_(gu if gu is not None else torch.zeros((R, C), device=dev))
@@ -81,6 +92,7 @@ def _backward(sim: Simulation, ckpt, nseg: int, T: int, S: int, gu, gv, dev, ker
     dtheta = torch.zeros(8, dtype=torch.float64, device=dev)
     if kernel is not None:
         sim.set_adjoint_kernel(*kernel)
+    sim.set_grad_mask(mask)
     if S < 0:  # ckpt holds the whole recorded trajectory
         sim.adjoint(ckpt, T, adj, tmp, dtheta)
         return adj, dtheta
@@ -98,14 +110,14 @@ class RDCNNFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, theta, T: int, bc: str = "zeroflux", ka: float = 1.0, S: int = 0,
-                adj_kernel=None):
+                adj_kernel=None, mask: int = 0xFF):
         x = x.detach().contiguous()
         T = int(T)
         S = choose_schedule(T, x.shape[0], x.shape[1], int(S), x.device)
         sim = Simulation(x, _gene(theta), bc, ka)
         u, v, ckpt, nseg = _forward(sim, T, S, x.device)
         ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S, ctx.ka = sim, ckpt, nseg, T, S, ka
-        ctx.adj_kernel = adj_kernel
+        ctx.adj_kernel, ctx.mask = adj_kernel, mask
         ctx.theta_meta = (theta.dtype, theta.device)
         return u, v
 
@@ -113,18 +125,19 @@ class RDCNNFunction(torch.autograd.Function):
     def backward(ctx, gu, gv):
         dev = ctx.ckpt.device
         adj, dtheta = _backward(ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S, gu, gv, dev,
-                                ctx.adj_kernel)
+                                ctx.adj_kernel, ctx.mask)
         gx = init_backward(adj, ctx.ka)
         ctx.sim.close()
         dt, dd = ctx.theta_meta
-        return gx, dtheta.to(device=dd, dtype=dt), None, None, None, None, None
+        return gx, dtheta.to(device=dd, dtype=dt), None, None, None, None, None, None
 
 
 class RDCNNStateFunction(torch.autograd.Function):
     """(u0, v0, theta) -> (u_T, v_T): T steps from an explicit state."""
 
     @staticmethod
-    def forward(ctx, u0, v0, theta, T: int, bc: str = "zeroflux", S: int = 0, adj_kernel=None):
+    def forward(ctx, u0, v0, theta, T: int, bc: str = "zeroflux", S: int = 0, adj_kernel=None,
+                mask: int = 0xFF):
         u0 = u0.detach().contiguous()
         v0 = v0.detach().contiguous()
         T = int(T)
@@ -132,7 +145,7 @@ class RDCNNStateFunction(torch.autograd.Function):
         sim = Simulation.from_state(u0, v0, _gene(theta), bc)
         u, v, ckpt, nseg = _forward(sim, T, S, u0.device)
         ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S = sim, ckpt, nseg, T, S
-        ctx.adj_kernel = adj_kernel
+        ctx.adj_kernel, ctx.mask = adj_kernel, mask
         ctx.theta_meta = (theta.dtype, theta.device)
         return u, v
 
@@ -140,17 +153,20 @@ class RDCNNStateFunction(torch.autograd.Function):
     def backward(ctx, gu, gv):
         dev = ctx.ckpt.device
         adj, dtheta = _backward(ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S, gu, gv, dev,
-                                ctx.adj_kernel)
+                                ctx.adj_kernel, ctx.mask)
         ctx.sim.close()
         dt, dd = ctx.theta_meta
-        return adj[0].clone(), adj[1].clone(), dtheta.to(device=dd, dtype=dt), None, None, None, None
+        return (adj[0].clone(), adj[1].clone(), dtheta.to(device=dd, dtype=dt), None, None, None,
+                None, None)
 
 
-def simulate(x, theta, T, bc="zeroflux", ka=1.0, S=0):
-    """Differentiable T-step run from u = v = ka x; returns (u_T, v_T)."""
-    return RDCNNFunction.apply(x, theta, T, bc, ka, S, None)
+def simulate(x, theta, T, bc="zeroflux", ka=1.0, S=0, grads=None):
+    """Differentiable T-step run from u = v = ka x; returns (u_T, v_T).
+    grads: parameter names whose gradients are formed (default all); the
+    others come back NaN in theta.grad."""
+    return RDCNNFunction.apply(x, theta, T, bc, ka, S, None, grad_mask(grads))
 
 
-def simulate_state(u0, v0, theta, T, bc="zeroflux", S=0):
+def simulate_state(u0, v0, theta, T, bc="zeroflux", S=0, grads=None):
     """Differentiable T-step run from (u0, v0); returns (u_T, v_T)."""
-    return RDCNNStateFunction.apply(u0, v0, theta, T, bc, S, None)
+    return RDCNNStateFunction.apply(u0, v0, theta, T, bc, S, None, grad_mask(grads))

@@ -40,7 +40,9 @@ struct AdjArgs {
     double *partial;      // [>= ntiles][NSUM], accumulated
 };
 
-template <int CPL, int KB, bool FAST>
+// LAMS: also sum the three lam-weighted products only dJ/ddt, dJ/dc and dJ/dk3
+// need (S_LU, S_LU3, S_LV).
+template <int CPL, int KB, bool FAST, bool LAMS>
 __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &t)
 {
     const int C = A.t.C, R = A.t.R, bc = A.t.bc;
@@ -56,9 +58,12 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &
     const int n_real = y1 - y0 + 2 * KB;
     const int n_iter = (n_real + 2) / 3 * 3;
 
-    float w[CPL];  // 1 for this lane's output cells, 0 for halo cells
+    // 1 for this lane's output cells, 0 for halo cells.  In full-width tiles a
+    // lane's columns are all output or all halo, so its sums are weighted once
+    // at the end; edge tiles weight each product.
+    float w[CPL];
 #pragma unroll
-    for (int e = 0; e < CPL; ++e) w[e] = t.owns(A.t, e);
+    for (int e = 0; e < CPL; ++e) w[e] = FAST ? 1.0f : t.owns(A.t, e);
 
     float bl[KB][3][CPL], bm[KB][3][CPL];  // lam, mu windows per level
     // State rows per level, in the same modulo-3 slots as the window: the row
@@ -116,15 +121,20 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &
                     const float rm_ = __builtin_fmaf(g.Dv, Lm, __builtin_fmaf(epsb, mu, -l));
                     dm[e] = __builtin_fmaf(g.dt, rm_, mu);
                     if (count) {  // halo cells enter with weight 0
-                        const float uw = w[e] * u, vw = w[e] * v;
+                        const float uw = FAST ? u : w[e] * u, vw = FAST ? v : w[e] * v;
                         acc[S_LLU] = __builtin_fmaf(Ll, uw, acc[S_LLU]);
                         acc[S_LMV] = __builtin_fmaf(Lm, vw, acc[S_LMV]);
-                        acc[S_LU] = __builtin_fmaf(l, uw, acc[S_LU]);
-                        acc[S_LU3] = __builtin_fmaf(l * uw, u2, acc[S_LU3]);
-                        acc[S_LV] = __builtin_fmaf(l, vw, acc[S_LV]);
+                        if (LAMS) {
+                            acc[S_LU] = __builtin_fmaf(l, uw, acc[S_LU]);
+                            acc[S_LU3] = __builtin_fmaf(l * uw, u2, acc[S_LU3]);
+                            acc[S_LV] = __builtin_fmaf(l, vw, acc[S_LV]);
+                        }
                         acc[S_MU] = __builtin_fmaf(mu, uw, acc[S_MU]);
                         acc[S_MV] = __builtin_fmaf(mu, vw, acc[S_MV]);
-                        acc[S_M] = __builtin_fmaf(w[e], mu, acc[S_M]);
+                        if (FAST)
+                            acc[S_M] += mu;
+                        else
+                            acc[S_M] = __builtin_fmaf(w[e], mu, acc[S_M]);
                     }
                 }
             }
@@ -157,24 +167,25 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &
     }
 
     // Wave reduction in double, fixed butterfly order; lane 0 adds to the tile.
+    const float wl = FAST ? t.owns(A.t, 0) : 1.0f;
 #pragma unroll
     for (int k = 0; k < NSUM; ++k) {
-        double s = (double)acc[k];
+        double s = (double)(acc[k] * wl);
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
         if (threadIdx.x == 0) A.partial[(size_t)t.tile * NSUM + k] += s;
     }
 }
 
-template <int CPL, int KB>
+template <int CPL, int KB, bool LAMS>
 __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs A)
 {
     Tile<CPL> t;
     if (!t.init(A.t)) return;
     if (t.fast)
-        adjoint_body<CPL, KB, true>(A, t);
+        adjoint_body<CPL, KB, true, LAMS>(A, t);
     else
-        adjoint_body<CPL, KB, false>(A, t);
+        adjoint_body<CPL, KB, false, LAMS>(A, t);
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(double *p, long long n)
@@ -187,7 +198,7 @@ __global__ __launch_bounds__(256) void zero_kernel(double *p, long long n)
 // One workgroup: sums the per-tile partials in a fixed order and adds the
 // gradients (order dt, a, b, eps, c, k3, Du, Dv) to dtheta.
 __global__ __launch_bounds__(256) void adjoint_finish_kernel(const double *partial, int ntiles,
-                                                             Gene g, double *dtheta)
+                                                             Gene g, unsigned mask, double *dtheta)
 {
     __shared__ double red[NSUM][256];
     double s[NSUM];
@@ -212,14 +223,17 @@ __global__ __launch_bounds__(256) void adjoint_finish_kernel(const double *parti
         const double LU3 = red[S_LU3][0], LV = red[S_LV][0], MU = red[S_MU][0];
         const double MV = red[S_MV][0], M = red[S_M][0];
         const double res = MU - b * MV + a * M;  // <mu', u - b v + a>
-        dtheta[0] += c * LU - k3 * LU3 - LV - eps * res + Du * LLU + Dv * LMV;  // dt
-        dtheta[1] += -dt * eps * M;                                             // a
-        dtheta[2] += dt * eps * MV;                                             // b
-        dtheta[3] += -dt * res;                                                 // eps
-        dtheta[4] += dt * LU;                                                   // c
-        dtheta[5] += -dt * LU3;                                                 // k3
-        dtheta[6] += dt * LLU;                                                  // Du
-        dtheta[7] += dt * LMV;                                                  // Dv
+        double d[8];
+        d[0] = c * LU - k3 * LU3 - LV - eps * res + Du * LLU + Dv * LMV;  // dt
+        d[1] = -dt * eps * M;                                             // a
+        d[2] = dt * eps * MV;                                             // b
+        d[3] = -dt * res;                                                 // eps
+        d[4] = dt * LU;                                                   // c
+        d[5] = -dt * LU3;                                                 // k3
+        d[6] = dt * LLU;                                                  // Du
+        d[7] = dt * LMV;                                                  // Dv
+        // Gradients outside the mask were not summed: mark them NaN.
+        for (int q = 0; q < 8; ++q) dtheta[q] = (mask >> q) & 1u ? dtheta[q] + d[q] : __builtin_nan("");
     }
 }
 
@@ -236,12 +250,21 @@ namespace {
 
 using AdjFn = void (*)(AdjArgs);
 
-template <int CPL, int... Ks>
+template <int CPL, bool LAMS, int... Ks>
 constexpr AdjFn pick(int k, std::integer_sequence<int, Ks...>)
 {
     AdjFn f = nullptr;
-    ((f = (k == Ks + 1) ? &adjoint_kernel<CPL, Ks + 1> : f), ...);
+    ((f = (k == Ks + 1) ? &adjoint_kernel<CPL, Ks + 1, LAMS> : f), ...);
     return f;
+}
+
+template <bool LAMS>
+AdjFn pick_adj(int cpl, int depth)
+{
+    if (cpl == 4) return pick<4, LAMS>(depth, std::make_integer_sequence<int, kMaxAdjDepthCpl4>{});
+    if (cpl == 2) return pick<2, LAMS>(depth, std::make_integer_sequence<int, kMaxAdjDepthCpl2>{});
+    if (cpl == 1) return pick<1, LAMS>(depth, std::make_integer_sequence<int, kMaxAdjDepthCpl1>{});
+    return nullptr;
 }
 
 unsigned grid1(long long n)
@@ -255,13 +278,9 @@ unsigned grid1(long long n)
 
 hipError_t launch_adjoint(const float *in, float *out, const float *states, long long q_top,
                           int R, int C, int bc, const Gene &g, const StreamGeom &geom,
-                          double *partial, hipStream_t s)
+                          double *partial, bool lam_sums, hipStream_t s)
 {
-    AdjFn f = nullptr;
-    if (geom.cpl == 4)
-        f = pick<4>(geom.depth, std::make_integer_sequence<int, kMaxAdjDepthCpl4>{});
-    else if (geom.cpl == 2)
-        f = pick<2>(geom.depth, std::make_integer_sequence<int, kMaxAdjDepthCpl2>{});
+    AdjFn f = lam_sums ? pick_adj<true>(geom.cpl, geom.depth) : pick_adj<false>(geom.cpl, geom.depth);
     if (!f || q_top < geom.depth - 1) return hipErrorInvalidValue;
     AdjArgs a;
     a.t = tile_args(R, C, bc, geom);
@@ -280,10 +299,10 @@ hipError_t launch_zero(double *p, long long n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_finish(const double *partial, int ntiles, const Gene &g, double *dtheta,
-                                 hipStream_t s)
+hipError_t launch_adjoint_finish(const double *partial, int ntiles, const Gene &g, unsigned mask,
+                                 double *dtheta, hipStream_t s)
 {
-    hipLaunchKernelGGL(adjoint_finish_kernel, dim3(1), dim3(256), 0, s, partial, ntiles, g,
+    hipLaunchKernelGGL(adjoint_finish_kernel, dim3(1), dim3(256), 0, s, partial, ntiles, g, mask,
                        dtheta);
     return hipGetLastError();
 }

@@ -23,6 +23,7 @@ struct rdcnn_sim {
     int kind;  // 0 automatic, 1 naive, 2 streamed
     int depth, cpl, seg_rows;
     int adj_depth, adj_cpl, adj_seg_rows;  // 0: automatic
+    unsigned grad_mask;                    // gradients rdcnn_adjoint forms (bit q: param q)
     double *partial;                       // adjoint per-tile partial sums
     long long partial_cap;                 // tiles it can hold
 };
@@ -77,17 +78,11 @@ rd::Gene to_gene(const rdcnn_params_t *p)
 void auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows, bool record)
 {
     *seg_rows = 0;
-    if (record) {
-        *cpl = 2;
-        *depth = 8;
-    } else if (h->R >= 2048 && h->C >= 2048) {
+    if (h->R >= 2048 && h->C >= 2048 && !record) {
         *cpl = 4;
         *depth = 8;
-    } else if ((long long)h->R * h->C >= 512LL * 512) {
-        *cpl = 2;
-        *depth = 4;
     } else {
-        *cpl = 2;
+        *cpl = 1;
         *depth = 8;
     }
 }
@@ -138,6 +133,9 @@ int run_steps(rdcnn_sim *h, long long n, float *rec)
     return RDCNN_OK;
 }
 
+// Gradients that need the lam-weighted sums: dt (bit 0), c (bit 4), k3 (bit 5).
+constexpr unsigned kLamSumGrads = (1u << 0) | (1u << 4) | (1u << 5);
+
 void adj_auto_config(const rdcnn_sim *, int *cpl, int *depth, int *seg_rows)
 {
     *cpl = 2;
@@ -184,6 +182,7 @@ int rdcnn_create(rdcnn_t *out, int rows, int cols, int bc, const rdcnn_params_t 
     h->adj_depth = 0;
     h->adj_cpl = 0;
     h->adj_seg_rows = 0;
+    h->grad_mask = 0xFFu;
     h->partial = nullptr;
     h->partial_cap = 0;
     hipError_t e = rd::launch_init(x_dev, ka, buf0_dev, (long long)rows * cols, h->stream);
@@ -217,8 +216,8 @@ int rdcnn_set_adjoint_kernel(rdcnn_t h, int depth, int cols_per_lane, int seg_ro
         h->adj_depth = h->adj_cpl = h->adj_seg_rows = 0;
         return RDCNN_OK;
     }
-    if (cols_per_lane != 2 && cols_per_lane != 4)
-        return fail(RDCNN_EINVAL, "rdcnn_set_adjoint_kernel: cols_per_lane %d not in {2,4}",
+    if (cols_per_lane != 1 && cols_per_lane != 2 && cols_per_lane != 4)
+        return fail(RDCNN_EINVAL, "rdcnn_set_adjoint_kernel: cols_per_lane %d not in {1,2,4}",
                     cols_per_lane);
     if (depth < 1 || depth > rd::max_adj_depth(cols_per_lane))
         return fail(RDCNN_EINVAL, "rdcnn_set_adjoint_kernel: depth %d out of range", depth);
@@ -275,7 +274,7 @@ int rdcnn_adjoint(rdcnn_t h, const float *states_dev, long long S, float *adj_de
         if (!rd::stream_geometry(h->R, h->C, cpl, k, seg, &geom))
             return fail(RDCNN_EINVAL, "rdcnn_adjoint: cannot tile %dx%d", h->R, h->C);
         e = rd::launch_adjoint(cur, other, states_dev, q_top, h->R, h->C, h->bc, h->g, geom,
-                               h->partial, h->stream);
+                               h->partial, (h->grad_mask & kLamSumGrads) != 0, h->stream);
         if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint: kernel launch");
         float *tmp = cur;
         cur = other;
@@ -288,8 +287,16 @@ int rdcnn_adjoint(rdcnn_t h, const float *states_dev, long long S, float *adj_de
                            hipMemcpyDeviceToDevice, h->stream);
         if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint: copy back");
     }
-    e = rd::launch_adjoint_finish(h->partial, (int)need, h->g, dtheta_dev, h->stream);
+    e = rd::launch_adjoint_finish(h->partial, (int)need, h->g, h->grad_mask, dtheta_dev, h->stream);
     if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint: finish");
+    return RDCNN_OK;
+}
+
+int rdcnn_set_grad_mask(rdcnn_t h, unsigned mask)
+{
+    if (!h) return fail(RDCNN_EINVAL, "rdcnn_set_grad_mask: NULL handle");
+    if (mask == 0 || mask > 0xFFu) return fail(RDCNN_EINVAL, "rdcnn_set_grad_mask: mask 0x%x", mask);
+    h->grad_mask = mask;
     return RDCNN_OK;
 }
 
@@ -351,8 +358,8 @@ int rdcnn_set_kernel(rdcnn_t h, int kind, int depth, int cols_per_lane, int seg_
         return RDCNN_OK;
     }
     if (kind != 2) return fail(RDCNN_EINVAL, "rdcnn_set_kernel: unknown kind %d", kind);
-    if (cols_per_lane != 2 && cols_per_lane != 4)
-        return fail(RDCNN_EINVAL, "rdcnn_set_kernel: cols_per_lane %d not in {2,4}", cols_per_lane);
+    if (cols_per_lane != 1 && cols_per_lane != 2 && cols_per_lane != 4)
+        return fail(RDCNN_EINVAL, "rdcnn_set_kernel: cols_per_lane %d not in {1,2,4}", cols_per_lane);
     if (depth < 1 || depth > rd::max_depth(cols_per_lane))
         return fail(RDCNN_EINVAL, "rdcnn_set_kernel: depth %d out of range for cols_per_lane %d",
                     depth, cols_per_lane);

@@ -93,6 +93,8 @@ hipError_t launch_batch(const BatchTile *tiles, const BatchInst *insts, int ntil
         f = pick<4>(depth, std::make_integer_sequence<int, kMaxDepthCpl4>{});
     else if (cpl == 2)
         f = pick<2>(depth, std::make_integer_sequence<int, kMaxDepthCpl2>{});
+    else if (cpl == 1)
+        f = pick<1>(depth, std::make_integer_sequence<int, kMaxDepthCpl1>{});
     if (!f || ntiles < 1) return hipErrorInvalidValue;
     BatchArgs a;
     a.tiles = tiles;
@@ -152,11 +154,13 @@ void drop_graph(rdcnn_batch *b)
     b->graph_T = -1;
 }
 
+// Defaults from a sweep of the 1024-instance parameter-sweep workload on MI355X
+// (two columns per lane, twelve steps per pass and 128-row tiles led).
 void batch_config(const rdcnn_batch *b, int *cpl, int *depth, int *seg)
 {
-    *cpl = b->cpl ? b->cpl : 4;
-    *depth = b->depth ? b->depth : 8;
-    *seg = b->seg_rows ? b->seg_rows : 64;
+    *cpl = b->cpl ? b->cpl : 2;
+    *depth = b->depth ? b->depth : 12;
+    *seg = b->seg_rows ? b->seg_rows : 128;
 }
 
 // Tile list for one pass depth: every instance cut into strips of wout output
@@ -321,7 +325,7 @@ int rdcnn_batch_set_kernel(rdcnn_batch_t b, int depth, int cols_per_lane, int se
     if (depth == 0 && cols_per_lane == 0 && seg_rows == 0) {
         b->cpl = b->depth = b->seg_rows = 0;
     } else {
-        if (cols_per_lane != 2 && cols_per_lane != 4)
+        if (cols_per_lane != 1 && cols_per_lane != 2 && cols_per_lane != 4)
             return bfail(RDCNN_EINVAL, "rdcnn_batch_set_kernel: cols_per_lane %d", cols_per_lane);
         if (depth < 1 || depth > rd::max_depth(cols_per_lane))
             return bfail(RDCNN_EINVAL, "rdcnn_batch_set_kernel: depth %d", depth);

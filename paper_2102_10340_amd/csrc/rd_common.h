@@ -47,17 +47,19 @@ __device__ __forceinline__ void cell_update(const Gene &g, float uc, float vc, f
 //             symmetric), so the ghost value next to an edge cell always equals
 //             the edge cell, which is the zero-flux rule, at every depth of a
 //             temporally blocked pass.
+// Written as fold loops rather than a modulo: an index inside the line costs
+// one compare, one within a halo of the edge one fold, and only lines shorter
+// than the halo fold more than once (a modulo would be if-converted into an
+// always-executed division on the scalar unit).
 __device__ __forceinline__ int map_index(int i, int n, int bc)
 {
-    if ((unsigned)i < (unsigned)n) return i;
     if (bc == BC_PERIODIC) {
-        int m = i % n;
-        return m < 0 ? m + n : m;
+        while (i < 0) i += n;
+        while (i >= n) i -= n;
+    } else {
+        while ((unsigned)i >= (unsigned)n) i = i < 0 ? -1 - i : 2 * n - 1 - i;
     }
-    const int p = 2 * n;
-    int m = i % p;
-    if (m < 0) m += p;
-    return m < n ? m : p - 1 - m;
+    return i;
 }
 
 // Lane i receives lane i-1's value (lane 0 receives 0): DPP wave_shr:1.

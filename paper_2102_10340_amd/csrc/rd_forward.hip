@@ -97,7 +97,7 @@ __global__ __launch_bounds__(64) void stream_step_kernel(StreamArgs A)
 
 bool stream_geometry(int R, int C, int cpl, int depth, int seg_rows, StreamGeom *g)
 {
-    if (cpl != 2 && cpl != 4) return false;
+    if (cpl != 1 && cpl != 2 && cpl != 4) return false;
     if (depth < 1 || depth > max_depth(cpl)) return false;
     g->cpl = cpl;
     g->depth = depth;
@@ -140,6 +140,7 @@ StreamFn pick_stream(int cpl, int depth)
 {
     if (cpl == 4) return pick<4, REC>(depth, std::make_integer_sequence<int, kMaxDepthCpl4>{});
     if (cpl == 2) return pick<2, REC>(depth, std::make_integer_sequence<int, kMaxDepthCpl2>{});
+    if (cpl == 1) return pick<1, REC>(depth, std::make_integer_sequence<int, kMaxDepthCpl1>{});
     return nullptr;
 }
 

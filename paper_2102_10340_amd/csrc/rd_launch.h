@@ -11,18 +11,23 @@ int set_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3
 
 // Largest number of time steps one register-streamed pass may take, per
 // columns-per-lane setting (bounded by the 256 architected VGPRs a wave has).
+constexpr int kMaxDepthCpl1 = 16;
 constexpr int kMaxDepthCpl2 = 16;
 constexpr int kMaxDepthCpl4 = 12;
 
-inline int max_depth(int cpl) { return cpl == 4 ? kMaxDepthCpl4 : cpl == 2 ? kMaxDepthCpl2 : 0; }
+inline int max_depth(int cpl)
+{
+    return cpl == 4 ? kMaxDepthCpl4 : cpl == 2 ? kMaxDepthCpl2 : cpl == 1 ? kMaxDepthCpl1 : 0;
+}
 
-// Same bound for the adjoint kernel (it also keeps one state row per level).
+// Same bound for the adjoint kernel (it also keeps state rows per level).
+constexpr int kMaxAdjDepthCpl1 = 8;
 constexpr int kMaxAdjDepthCpl2 = 8;
 constexpr int kMaxAdjDepthCpl4 = 6;
 
 inline int max_adj_depth(int cpl)
 {
-    return cpl == 4 ? kMaxAdjDepthCpl4 : cpl == 2 ? kMaxAdjDepthCpl2 : 0;
+    return cpl == 4 ? kMaxAdjDepthCpl4 : cpl == 2 ? kMaxAdjDepthCpl2 : cpl == 1 ? kMaxAdjDepthCpl1 : 0;
 }
 
 // Number of partial sums the adjoint keeps per tile.
@@ -30,7 +35,7 @@ constexpr int kAdjSums = 8;
 
 // Geometry of one register-streamed pass over an R x C grid.
 struct StreamGeom {
-    int cpl;     // columns held by one lane (2 or 4)
+    int cpl;     // columns held by one lane (1, 2 or 4)
     int depth;   // time steps done in the pass (K)
     int kpad;    // left/right halo columns of a strip (K rounded up to cpl)
     int wout;    // output columns of a strip (64*cpl - 2*kpad)
@@ -61,14 +66,16 @@ hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, cons
 
 // `geom.depth` reverse steps: (lam, mu) `in` -> `out`, reading states
 // states[q_top], states[q_top-1], ...; adds each tile's eight sums to partial.
+// lam_sums: also form the sums only dJ/ddt, dJ/dc and dJ/dk3 need.
 hipError_t launch_adjoint(const float *in, float *out, const float *states, long long q_top,
                           int R, int C, int bc, const Gene &g, const StreamGeom &geom,
-                          double *partial, hipStream_t s);
+                          double *partial, bool lam_sums, hipStream_t s);
 
 hipError_t launch_zero(double *p, long long n, hipStream_t s);
 
-// Fold ntiles rows of partial sums into the eight gradients, added to dtheta.
-hipError_t launch_adjoint_finish(const double *partial, int ntiles, const Gene &g,
+// Fold ntiles rows of partial sums into the eight gradients, added to dtheta
+// for the bits of mask (dt, a, b, eps, c, k3, Du, Dv = bits 0..7); NaN elsewhere.
+hipError_t launch_adjoint_finish(const double *partial, int ntiles, const Gene &g, unsigned mask,
                                  double *dtheta, hipStream_t s);
 
 // One launch of the batched kernel: `depth` steps for every tile of the list.

@@ -21,7 +21,7 @@
 namespace rd {
 
 template <int CPL>
-using vecf = float __attribute__((ext_vector_type(CPL)));
+using vecf = float __attribute__((ext_vector_type(CPL)));  // CPL = 2 or 4
 
 // Third word of a raw (unswizzled, stride 0) buffer resource on gfx9-family
 // GPUs: 32-bit data format, no swizzle.
@@ -38,6 +38,12 @@ struct Buf {
 
 template <int CPL>
 __device__ __forceinline__ void buf_load(const Buf &b, unsigned voff, unsigned soff, float (&x)[CPL]);
+
+template <>
+__device__ __forceinline__ void buf_load<1>(const Buf &b, unsigned voff, unsigned soff, float (&x)[1])
+{
+    x[0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, voff, soff, 0));
+}
 
 template <>
 __device__ __forceinline__ void buf_load<2>(const Buf &b, unsigned voff, unsigned soff, float (&x)[2])
@@ -59,6 +65,12 @@ __device__ __forceinline__ void buf_load<4>(const Buf &b, unsigned voff, unsigne
 
 template <int CPL>
 __device__ __forceinline__ void buf_store(const Buf &b, unsigned voff, unsigned soff, const float (&x)[CPL]);
+
+template <>
+__device__ __forceinline__ void buf_store<1>(const Buf &b, unsigned voff, unsigned soff, const float (&x)[1])
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x[0]), b.r, voff, soff, 0);
+}
 
 template <>
 __device__ __forceinline__ void buf_store<2>(const Buf &b, unsigned voff, unsigned soff, const float (&x)[2])

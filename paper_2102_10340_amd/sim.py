@@ -78,6 +78,11 @@ class Simulation:
         check(lib.rdcnn_adjoint(self._h, states.data_ptr() if S > 0 else None, int(S),
                                 adj.data_ptr(), adj_tmp.data_ptr(), dtheta.data_ptr()))
 
+    def set_grad_mask(self, mask: int) -> None:
+        """Parameter gradients the adjoint forms (bit q = parameter q in the order
+        dt, a, b, eps, c, k3, Du, Dv); the others come back NaN."""
+        check(lib.rdcnn_set_grad_mask(self._h, int(mask)))
+
     def set_adjoint_kernel(self, depth: int = 0, cols_per_lane: int = 0, seg_rows: int = 0) -> None:
         check(lib.rdcnn_set_adjoint_kernel(self._h, int(depth), int(cols_per_lane), int(seg_rows)))
 

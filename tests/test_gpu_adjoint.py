@@ -48,7 +48,8 @@ def gpu_record(x, gene, bc, T, kernel=None):
     return sim, states
 
 
-@pytest.mark.parametrize("kernel", [(1, 0, 0, 0), (2, 8, 4, 0), (2, 5, 2, 3), (2, 16, 2, 0)],
+@pytest.mark.parametrize("kernel", [(1, 0, 0, 0), (2, 8, 4, 0), (2, 5, 2, 3), (2, 16, 2, 0),
+                                    (2, 6, 1, 0)],
                          ids=lambda k: "k%d_d%d_c%d_h%d" % k)
 @pytest.mark.parametrize("bc", BCS)
 @pytest.mark.parametrize("shape", [(1, 1), (5, 9), (40, 300), (129, 257)], ids=lambda s: "%dx%d" % s)
@@ -86,7 +87,8 @@ def _adjoint_case(R, C, bc, gene, T, kernel, seed=0):
     return got, dth.cpu().numpy(), l0, m0, dp
 
 
-@pytest.mark.parametrize("kernel", [None, (4, 4, 0), (8, 2, 0), (3, 4, 5), (1, 2, 1), (6, 4, 7)],
+@pytest.mark.parametrize("kernel", [None, (4, 4, 0), (8, 2, 0), (3, 4, 5), (1, 2, 1), (6, 4, 7),
+                                    (4, 1, 0), (8, 1, 3)],
                          ids=lambda k: "auto" if k is None else "d%d_c%d_h%d" % k)
 @pytest.mark.parametrize("bc", BCS)
 @pytest.mark.parametrize("shape", [(1, 1), (3, 70), (33, 17), (64, 64), (131, 300)],
@@ -173,3 +175,26 @@ def test_differentiation_workload_full_size():
     for i, k in enumerate(KEYS):
         if k in ("Du", "Dv", "eps"):
             assert abs(theta.grad[i].item() - dp[k]) <= 1e-3 * abs(dp[k]), (k, theta.grad[i].item(), dp[k])
+
+
+def test_gradient_mask_subset_equal_and_rest_nan():
+    """Forming only dJ/dDu, dJ/dDv, dJ/deps (no lam-weighted sums) gives the same
+    values as forming all eight; the rest come back NaN; dJ/dx is unchanged."""
+    from paper_2102_10340_amd import simulate
+    R, C, T = 70, 300, 60
+    g = W.gene(Du=0.09, Dv=0.7)
+    x = W.uniform_x(R, C, 21)
+    w = torch.from_numpy(np.random.default_rng(3).standard_normal((R, C)).astype(np.float32)).cuda()
+    out = []
+    for grads in (None, ("Du", "Dv", "eps")):
+        xt = torch.from_numpy(x).cuda().requires_grad_(True)
+        theta = torch.tensor([g[k] for k in KEYS], dtype=torch.float64, requires_grad=True)
+        u, v = simulate(xt, theta, T, "zeroflux", grads=grads)
+        (u * w).sum().backward()
+        out.append((xt.grad.cpu().numpy(), theta.grad.numpy()))
+    assert np.array_equal(out[0][0], out[1][0])
+    for i, k in enumerate(KEYS):
+        if k in ("Du", "Dv", "eps"):
+            assert abs(out[0][1][i] - out[1][1][i]) <= 1e-9 * max(1.0, abs(out[0][1][i])), k
+        else:
+            assert np.isnan(out[1][1][i]) and np.isfinite(out[0][1][i]), k

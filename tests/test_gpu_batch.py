@@ -38,7 +38,8 @@ def _mixed(seed, n=11):
     return xs, genes
 
 
-@pytest.mark.parametrize("kernel", [None, (8, 4, 0), (4, 2, 16), (3, 4, 5), (16, 2, 200)],
+@pytest.mark.parametrize("kernel", [None, (8, 4, 0), (4, 2, 16), (3, 4, 5), (16, 2, 200),
+                                    (6, 1, 32)],
                          ids=lambda k: "auto" if k is None else "d%d_c%d_h%d" % k)
 @pytest.mark.parametrize("bc", ["zeroflux", "periodic"])
 def test_batch_instances_bitwise(bc, kernel):

@@ -59,6 +59,8 @@ KERNELS = [
     (2, 1, 2, 1),   # one row per segment, one step per pass
     (2, 12, 4, 7),
     (2, 5, 2, 3),
+    (2, 4, 1, 0),   # one column per lane
+    (2, 16, 1, 2),
 ]
 SHAPES = [(1, 1), (1, 7), (7, 1), (2, 2), (3, 5), (17, 33), (64, 64), (37, 257), (130, 515), (256, 256)]
 
