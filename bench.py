@@ -49,6 +49,8 @@ def parse():
                     help="first run a plain device copy of this size (scales HBM counters)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the differentiation and parameter-sweep workloads")
+    ap.add_argument("--only-extra", choices=["fwd_bwd", "batched", "plain", "edge"],
+                    help="run just this extra workload after the forward steps (profiling)")
     return ap.parse_args()
 
 
@@ -62,10 +64,12 @@ def measured_traffic(kernel_prefix: str):
             rec = json.load(f)
         if rec.get("kernel") != kernel_prefix:
             continue
-        src = os.path.join(ROOT, rec["source"])
-        with open(src, "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
-                return None
+        h = hashlib.sha256()
+        for rel in rec["sources"]:
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != rec["sources_sha256"]:
+            return None
         return rec["traffic_bytes_per_launch"]
     return None
 
@@ -160,6 +164,71 @@ def bench_batched(stream, per_class=4):
             "per_instance_gcells": cells * T / t_single / 1e9, "per_instance_s_est": t_single,
             "speedup_vs_per_instance": t_single / tb, "sampled_instances_bitwise_equal": same,
             "baseline_sample": f"{per_class} instances per size class, scaled by class counts"}
+
+
+def bench_plain(stream):
+    """Plain method: 256x256, T=1000, zero-flux, x ~ U[-1,1] (seed 0)."""
+    import torch
+    from paper_2102_10340_amd import Simulation
+    N, T = 256, 1000
+    x = torch.from_numpy(W.uniform_x(N, N, 0)).cuda()
+    sim = Simulation(x, W.PLAIN_GENE, "zeroflux")
+    sim.step(T)
+    t = min(_timed(lambda: sim.step(T), stream) for _ in range(3))
+    sim.close()
+    return {"workload": "256x256 zero-flux, T=1000, x~U[-1,1]", "gcells": N * N * T / t / 1e9,
+            "ms": t * 1e3}
+
+
+def bench_edge_fit(stream, n_img=64, iters=4):
+    """Edge detection fitted by gradient: 64 synthetic 1024x1024 images (20..60
+    random rectangles of levels U[-1,1] plus N(0, 0.05^2) noise), x = image,
+    T = 50, zero-flux; Du, Dv and epsilon (shared by all images) fitted by Adam
+    to the normalized Sobel magnitude of the clean images.  Reports the loss
+    curve and the fwd+bwd rate over all images."""
+    import torch
+    from paper_2102_10340_amd import simulate
+    N, T = 1024, 50
+    imgs, targets = [], []
+    for i in range(n_img):
+        noisy, clean = W.rect_image(N, N, 500 + i)
+        imgs.append(torch.from_numpy(noisy).cuda())
+        targets.append(torch.from_numpy(W.sobel_target(clean)).cuda())
+    g = W.PLAIN_GENE
+    p = torch.tensor([g["Du"], g["Dv"], -g["eps"]], dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=0.02)
+    losses, times = [], []
+    for _ in range(iters):
+        opt.zero_grad()
+        theta = torch.stack([torch.tensor(g["dt"], dtype=torch.float64),
+                             torch.tensor(g["a"], dtype=torch.float64),
+                             torch.tensor(g["b"], dtype=torch.float64), -p[2],
+                             torch.tensor(g["c"], dtype=torch.float64),
+                             torch.tensor(g["k3"], dtype=torch.float64), p[0], p[1]])
+
+        def step():
+            total = 0.0
+            for x, tg in zip(imgs, targets):
+                u, _ = simulate(x, theta, T, "zeroflux", grads=("Du", "Dv", "eps"))
+                loss = ((u - tg) ** 2).mean() / n_img
+                loss.backward(retain_graph=True)
+                total += float(loss)
+            return total
+
+        t0 = time.perf_counter()
+        losses.append(step())
+        stream.synchronize()
+        times.append(time.perf_counter() - t0)
+        opt.step()
+        with torch.no_grad():
+            p[0].clamp_(0.0, 2.4)
+            p[1].clamp_(0.0, 2.4)
+            p[2].clamp_(1e-3, 1.0)
+    t = min(times)
+    return {"workload": f"{n_img} images 1024x1024, T=50, fit Du, Dv, eps by Adam to Sobel targets",
+            "loss_curve": losses, "params_final": {"Du": float(p[0]), "Dv": float(p[1]),
+                                                   "epsilon": float(p[2])},
+            "fwd_bwd_gcells": n_img * N * N * T / t / 1e9, "iter_s": t}
 
 
 def cpu_baseline(budget_s: float):
@@ -270,8 +339,14 @@ def main():
     if not args.no_extra:
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
-            out["fwd_bwd"] = bench_fwd_bwd(stream)
-            out["batched"] = bench_batched(stream)
+            if args.only_extra in (None, "fwd_bwd"):
+                out["fwd_bwd"] = bench_fwd_bwd(stream)
+            if args.only_extra in (None, "batched"):
+                out["batched"] = bench_batched(stream)
+            if args.only_extra in (None, "plain"):
+                out["plain"] = bench_plain(stream)
+            if args.only_extra in (None, "edge"):
+                out["edge_fit"] = bench_edge_fit(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -13,6 +13,7 @@ _EXPORTS = {
     "LIB_PATH": "._lib", "Simulation": ".sim", "init_backward": ".sim",
     "RDCNNFunction": ".autograd", "RDCNNStateFunction": ".autograd", "simulate": ".autograd",
     "simulate_state": ".autograd", "default_segment": ".autograd", "Batch": ".batch",
+    "tune": ".tune",
 }
 
 __all__ = sorted(_EXPORTS)
@@ -22,4 +23,5 @@ def __getattr__(name):
     mod = _EXPORTS.get(name)
     if mod is None:
         raise AttributeError(name)
-    return getattr(importlib.import_module(mod, __name__), name)
+    m = importlib.import_module(mod, __name__)
+    return m if mod == "." + name else getattr(m, name)

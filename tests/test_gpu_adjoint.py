@@ -198,3 +198,28 @@ def test_gradient_mask_subset_equal_and_rest_nan():
             assert abs(out[0][1][i] - out[1][1][i]) <= 1e-9 * max(1.0, abs(out[0][1][i])), k
         else:
             assert np.isnan(out[1][1][i]) and np.isfinite(out[0][1][i]), k
+
+
+def test_shared_parameters_over_many_images():
+    """Gradients of a loss summed over several images that share the parameters
+    (the edge-detection fit) equal the sum of the oracle's per-image gradients."""
+    from paper_2102_10340_amd import simulate
+    R, C, T = 48, 70, 30
+    g = W.gene(Du=0.1, Dv=0.5)
+    theta = torch.tensor([g[k] for k in KEYS], dtype=torch.float64, requires_grad=True)
+    ref = {k: 0.0 for k in KEYS}
+    for i in range(3):
+        noisy, clean = W.rect_image(R, C, 40 + i)
+        tgt = W.sobel_target(clean)
+        xt = torch.from_numpy(noisy).cuda()
+        u, _ = simulate(xt, theta, T, "zeroflux")
+        loss = ((u - torch.from_numpy(tgt).cuda()) ** 2).mean()
+        loss.backward()
+        uT = u.detach().cpu().numpy().astype(np.float64)
+        lam = 2.0 * (uT - tgt) / (R * C)
+        _, _, dp, _, _ = oracle.grad(noisy, noisy, g, "zeroflux", T, lam, np.zeros_like(lam), traj="f32")
+        for k in KEYS:
+            ref[k] += dp[k]
+    scale = max(abs(v) for v in ref.values())
+    for i, k in enumerate(KEYS):
+        assert abs(theta.grad[i].item() - ref[k]) <= 1e-3 * max(abs(ref[k]), 1e-3 * scale), k

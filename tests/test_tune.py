@@ -1,0 +1,57 @@
+"""Autotuner: cache keys, candidate lists and the JSON round trip (CPU), and a
+small tuning run whose chosen settings keep the results bit-exact (GPU)."""
+import json
+
+import numpy as np
+import pytest
+
+
+def test_candidates_respect_depth_limits():
+    from paper_2102_10340_amd import tune
+    for mode in ("forward", "record", "adjoint", "batch"):
+        c = tune.candidates(mode, 1024, 1024)
+        assert c and len(set(c)) == len(c)
+        lim = tune.MAX_ADJ_DEPTH if mode == "adjoint" else tune.MAX_DEPTH
+        assert all(1 <= d <= lim[cpl] and cpl in (1, 2, 4) and s >= 0 for d, cpl, s in c)
+    # narrow grids do not try strips much wider than themselves
+    assert all(cpl == 1 for _, cpl, _ in tune.candidates("forward", 64, 16))
+
+
+def test_cache_round_trip(tmp_path, monkeypatch):
+    from paper_2102_10340_amd import tune
+    path = tmp_path / "t.json"
+    monkeypatch.setenv("RDCNN_TUNE_CACHE", str(path))
+    tune.save({"a/forward/8x8/zeroflux": {"depth": 4, "cols_per_lane": 2, "seg_rows": 0, "gcells": 1.0}})
+    tune.save({"a/adjoint/8x8/zeroflux": {"depth": 2, "cols_per_lane": 1, "seg_rows": 8, "gcells": 2.0}})
+    data = json.load(open(path))
+    assert set(data) == {"a/forward/8x8/zeroflux", "a/adjoint/8x8/zeroflux"}
+    assert tune.lookup("a/adjoint/8x8/zeroflux") == (2, 1, 8)
+    assert tune.lookup("missing") is None
+    assert tune.batch_key([(2, 3), (4, 5), (2, 3)], "periodic").endswith("/batch/2x3*2,4x5*1/periodic")
+
+
+def test_shipped_cache_is_valid():
+    from paper_2102_10340_amd import tune
+    for k, e in tune.load(tune.SHIPPED).items():
+        mode = k.split("/")[1]
+        lim = tune.MAX_ADJ_DEPTH if mode == "adjoint" else tune.MAX_DEPTH
+        assert e["cols_per_lane"] in (1, 2, 4) and 1 <= e["depth"] <= lim[e["cols_per_lane"]], k
+
+
+@pytest.mark.gpu
+def test_tuned_settings_stay_bitwise(tmp_path, monkeypatch):
+    import torch
+    import oracle
+    import workloads as W
+    from paper_2102_10340_amd import Simulation, tune
+    monkeypatch.setenv("RDCNN_TUNE_CACHE", str(tmp_path / "t.json"))
+    best, res = tune.tune("forward", 96, 200, "zeroflux", budget_s=5.0)
+    assert best in res and all(v > 0 for v in res.values())
+    x = W.uniform_x(96, 200, 2)
+    sim = Simulation(torch.from_numpy(x).cuda(), W.PLAIN_GENE, "zeroflux")
+    assert tune.apply(sim)
+    sim.step(30)
+    u, v = sim.read_host()
+    sim.close()
+    ou, ov = oracle.run(*oracle.init_state(x, 1.0), W.PLAIN_GENE, "zeroflux", 30, "f32")
+    assert np.array_equal(u, ou) and np.array_equal(v, ov)
