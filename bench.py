@@ -49,7 +49,8 @@ def parse():
                     help="first run a plain device copy of this size (scales HBM counters)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the differentiation and parameter-sweep workloads")
-    ap.add_argument("--only-extra", choices=["fwd_bwd", "batched", "plain", "edge"],
+    ap.add_argument("--only-extra", choices=["fwd_bwd", "batched", "small_batch", "plain", "edge",
+                                                   "table1"],
                     help="run just this extra workload after the forward steps (profiling)")
     return ap.parse_args()
 
@@ -166,6 +167,49 @@ def bench_batched(stream, per_class=4):
             "baseline_sample": f"{per_class} instances per size class, scaled by class counts"}
 
 
+def bench_small_batch(stream, per_instance_sample=8):
+    """Many small grids: 1024 instances of 128x128 (the paper's smallest Table I
+    side), per-instance Du ~ U[0.01,0.2], Dv ~ U[0.2,1], epsilon ~ U[0.02,0.2],
+    zero-flux, x ~ U[-1,1] per instance, T = 10^4.  Three ways: the in-LDS
+    kernel (each instance whole in one workgroup's LDS for all steps), the
+    streamed batch kernel replayed from a graph, and one instance at a time
+    (sampled, scaled by the count).  The LDS and streamed results are compared
+    bit for bit."""
+    import torch
+    from paper_2102_10340_amd import Batch, Simulation
+    T = 10000
+    inst = W.sweep_instances(1024, 7, sides=(128,))
+    xs = [torch.from_numpy(W.uniform_x(d["rows"], d["cols"], d["seed"])).cuda() for d in inst]
+    genes = [d["gene"] for d in inst]
+    cells = sum(d["rows"] * d["cols"] for d in inst)
+    lds = Batch(xs, genes, "zeroflux")
+    n_lds = lds.lds_instances()
+    t_lds = _timed(lambda: lds.step(T), stream)
+    st = Batch(xs, genes, "zeroflux")
+    st.use_lds(False)
+    st.use_graph(True)
+    t_st = _timed(lambda: st.step(T), stream)  # includes the one-off graph capture
+    same = all(bool(torch.equal(lds.state(i), st.state(i))) for i in range(len(inst)))
+    st.step(T)  # steps T..2T from the captured graph
+    t_st = min(t_st, _timed(lambda: st.step(T), stream))
+    lds.close()
+    st.close()
+    ts = []
+    for i in range(per_instance_sample):
+        sim = Simulation(xs[i], genes[i], "zeroflux")
+        sim.step(100)
+        ts.append(_timed(lambda: sim.step(T), stream))
+        sim.close()
+    t_one = sum(ts) / len(ts) * len(inst)
+    return {"workload": "1024 instances 128x128, per-instance Du/Dv/eps, zero-flux, T=10000",
+            "in_lds_instances": n_lds, "in_lds_gcells": cells * T / t_lds / 1e9,
+            "in_lds_s": t_lds, "streamed_graph_gcells": cells * T / t_st / 1e9,
+            "streamed_s": t_st, "per_instance_gcells": cells * T / t_one / 1e9,
+            "per_instance_s_est": t_one, "lds_vs_streamed": t_st / t_lds,
+            "lds_vs_per_instance": t_one / t_lds, "lds_equals_streamed_bitwise": same,
+            "baseline_sample": f"{per_instance_sample} instances run alone, scaled by 1024"}
+
+
 def bench_plain(stream):
     """Plain method: 256x256, T=1000, zero-flux, x ~ U[-1,1] (seed 0)."""
     import torch
@@ -229,6 +273,32 @@ def bench_edge_fit(stream, n_img=64, iters=4):
             "loss_curve": losses, "params_final": {"Du": float(p[0]), "Dv": float(p[1]),
                                                    "epsilon": float(p[2])},
             "fwd_bwd_gcells": n_img * N * N * T / t / 1e9, "iter_s": t}
+
+
+# Table I of the paper: PyCUDA on a Tesla P100-PCIE, 10^4 iterations of the
+# default gene, Mcells/s per grid side.
+PAPER_TABLE1_PYCUDA = {128: 470, 256: 1941, 512: 7581, 1024: 13059, 2048: 14198, 4096: 14545}
+
+
+def bench_paper_table1(stream):
+    """The paper's Table I workload: the default gene (a=-0.3, b=1.3, eps=-0.1,
+    c=1, k3=1/3, Du=0.06, Dv=1, dt=0.1), periodic boundary, random 11x11 centre
+    patch, 10^4 iterations, N = 128 ... 4096; Mcells/s next to the paper's
+    PyCUDA figures (P100)."""
+    import torch
+    from paper_2102_10340_amd import Simulation
+    T = 10000
+    out = {}
+    for N, ref in PAPER_TABLE1_PYCUDA.items():
+        x = torch.from_numpy(W.centre_patch_x(N, N, 11, 0)).cuda()
+        sim = Simulation(x, W.gene(W.PAPER_DEFAULT_GENE), "periodic")
+        sim.step(200)
+        t = _timed(lambda: sim.step(T), stream)
+        sim.close()
+        rate = N * N * T / t / 1e6
+        out[str(N)] = {"mcells_s": rate, "s": t, "paper_pycuda_p100_mcells_s": ref,
+                       "ratio": rate / ref}
+    return out
 
 
 def cpu_baseline(budget_s: float):
@@ -343,10 +413,14 @@ def main():
                 out["fwd_bwd"] = bench_fwd_bwd(stream)
             if args.only_extra in (None, "batched"):
                 out["batched"] = bench_batched(stream)
+            if args.only_extra in (None, "small_batch"):
+                out["small_batch"] = bench_small_batch(stream)
             if args.only_extra in (None, "plain"):
                 out["plain"] = bench_plain(stream)
             if args.only_extra in (None, "edge"):
                 out["edge_fit"] = bench_edge_fit(stream)
+            if args.only_extra in (None, "table1"):
+                out["paper_table1"] = bench_paper_table1(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

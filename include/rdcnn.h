@@ -232,6 +232,19 @@ int rdcnn_batch_set_kernel(rdcnn_batch_t b, int depth, int cols_per_lane, int se
  */
 int rdcnn_batch_use_graph(rdcnn_batch_t b, int on);
 
+/*
+ * rdcnn_batch_use_lds -- on != 0 (the default): instances small enough to sit
+ * whole in one workgroup's LDS (at most 16384 cells, (rows+2)*(cols+2) pairs of
+ * floats within the device's per-workgroup LDS) run all T steps of a
+ * rdcnn_batch_step call in one launch, reading and writing HBM once.  Results
+ * are bit-identical either way.  Errors: RDCNN_EINVAL, RDCNN_ENOMEM.
+ */
+int rdcnn_batch_use_lds(rdcnn_batch_t b, int on);
+
+/* rdcnn_batch_lds_instances -- *count = number of instances that the in-LDS
+ * kernel runs under the current setting.  Errors: RDCNN_EINVAL (NULL). */
+int rdcnn_batch_lds_instances(rdcnn_batch_t b, int *count);
+
 /* rdcnn_batch_destroy -- release the batch (not the caller's buffers).  NULL is a no-op. */
 int rdcnn_batch_destroy(rdcnn_batch_t b);
 

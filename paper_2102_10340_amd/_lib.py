@@ -61,6 +61,8 @@ _SIGS = {
     "rdcnn_batch_current": [_P, _PP],
     "rdcnn_batch_set_kernel": [_P, _I, _I, _I],
     "rdcnn_batch_use_graph": [_P, _I],
+    "rdcnn_batch_use_lds": [_P, _I],
+    "rdcnn_batch_lds_instances": [_P, ctypes.POINTER(ctypes.c_int)],
     "rdcnn_batch_destroy": [_P],
 }
 for _name, _args in _SIGS.items():

@@ -63,6 +63,16 @@ class Batch:
     def set_kernel(self, depth: int = 0, cols_per_lane: int = 0, seg_rows: int = 0) -> None:
         check(lib.rdcnn_batch_set_kernel(self._h, int(depth), int(cols_per_lane), int(seg_rows)))
 
+    def use_lds(self, on: bool = True) -> None:
+        """Run instances that fit one workgroup's LDS whole, all steps in one launch."""
+        check(lib.rdcnn_batch_use_lds(self._h, 1 if on else 0))
+
+    def lds_instances(self) -> int:
+        """How many instances the in-LDS kernel runs."""
+        n = ctypes.c_int()
+        check(lib.rdcnn_batch_lds_instances(self._h, ctypes.byref(n)))
+        return n.value
+
     def use_graph(self, on: bool = True) -> None:
         check(lib.rdcnn_batch_use_graph(self._h, 1 if on else 0))
 

@@ -71,6 +71,130 @@ __global__ __launch_bounds__(64) void batch_step_kernel(BatchArgs B)
         stream_body<CPL, K, false, false>(A, t);
 }
 
+// ---------------------------------------------------------------- in-LDS instances
+//
+// A small instance is held whole in one workgroup's LDS for all T steps: one
+// HBM read at the start, one write at the end.  The LDS frame is (R+2) x (C+2)
+// (u, v) pairs with a ghost ring; the threads owning edge cells rewrite the
+// ghost cells after every step (a copy of the edge cell for zero-flux, of the
+// opposite edge for periodic), so the stencil reads fixed offsets.  Thread t
+// owns column t mod C and a run of m = ceil(R / s) consecutive rows of it
+// (s = 1024 / C runs per column), walking down the run with the north and
+// centre values in registers: three LDS reads per cell.  The new values are
+// held in registers until every thread has read the old ones.  Same
+// cell_update as every other kernel, so results are bit-identical.
+constexpr int kLdsThreads = 1024;
+constexpr int kLdsRun = 16;  // longest run of rows per thread
+
+// Padded-frame offsets, relative to a cell of the first (left) or last (right)
+// column, of the ghost cell that copies it: zero-flux, the ghost beside it;
+// periodic, the ghost beyond the opposite edge.  0 for a cell not on that edge
+// (a one-column grid is on both).
+__device__ __forceinline__ int ghost_left(int c, int C, bool per)
+{
+    return c == 0 ? (per ? C : -1) : 0;
+}
+__device__ __forceinline__ int ghost_right(int c, int C, bool per)
+{
+    return c == C - 1 ? (per ? -C : 1) : 0;
+}
+
+__global__ __launch_bounds__(kLdsThreads) void batch_lds_kernel(const BatchInst *insts,
+                                                                const int *ids, const float *in,
+                                                                float *out, int bc, long long T)
+{
+    extern __shared__ float2 sm[];
+    const BatchInst I = insts[ids[blockIdx.x]];
+    const int R = I.R, C = I.C, n = R * C, P = C + 2;
+    const bool per = bc == BC_PERIODIC;
+    const Gene g = I.g;
+    const int runs = kLdsThreads / C;     // host guarantees C <= kLdsThreads
+    const int m = (R + runs - 1) / runs;  // host guarantees m <= kLdsRun
+    const int t = (int)threadIdx.x;
+    const int c = t % C;
+    // Every thread walks m cells (a uniform trip count keeps the loop in
+    // scalar branches); threads past runs * C walk the first run again, and
+    // cells at rows >= R (frame rows up to runs * m, which the host sizes the
+    // frame for) are computed from whatever the frame holds but never stored.
+    const int r0 = t < runs * C ? (t / C) * m : 0;
+    const int len = t < runs * C ? max(0, min(m, R - r0)) : 0;  // cells this thread stores
+    const float *iu = in + I.off;
+    const float *iv = iu + n;
+    float *ou = out + I.off;
+    float *ov = ou + n;
+    const int base = (r0 + 1) * P + c + 1;  // padded index of the run's first cell
+    const int dl = ghost_left(c, C, per), dr = ghost_right(c, C, per);
+    // row ghosts: the top row's copy goes to row R (periodic) or -1, the
+    // bottom row's to row -1 or R
+    const int top_ghost = len > 0 && r0 == 0 ? (per ? base + R * P : base - P) : -1;
+    const int bot_ghost = len > 0 && r0 + len == R ? (per ? c + 1 : base + len * P) : -1;
+    for (int i = 0; i < len; ++i) {
+        const int r = r0 + i;
+        const float2 w = make_float2(iu[r * C + c], iv[r * C + c]);
+        sm[base + i * P] = w;
+        if (dl) sm[base + i * P + dl] = w;
+        if (dr) sm[base + i * P + dr] = w;
+    }
+    if (top_ghost >= 0) sm[top_ghost] = sm[base];
+    if (bot_ghost >= 0) sm[bot_ghost] = sm[base + (len - 1) * P];
+    __syncthreads();
+    for (long long step = 0; step < T; ++step) {
+        float2 nw[kLdsRun];
+        // Opaque copy of the base: stops the compiler from precomputing all
+        // 16 x 4 frame addresses outside the step loop (they would not fit in
+        // registers); each cell then costs one address add.
+        int pk = base;
+        asm volatile("" : "+v"(pk));
+        float2 nn = sm[pk - P], ce = sm[pk];
+#pragma unroll
+        for (int i = 0; i < kLdsRun; ++i) {
+            if (i < m) {
+                const float2 ss = sm[pk + P], ww = sm[pk - 1], ee = sm[pk + 1];
+                pk += P;
+                float uo, vo;
+                cell_update(g, ce.x, ce.y, nn.x, ss.x, ww.x, ee.x, nn.y, ss.y, ww.y, ee.y, uo,
+                            vo);
+                nw[i] = make_float2(uo, vo);
+                nn = ce;
+                ce = ss;
+            }
+        }
+        __syncthreads();
+        pk = base;
+        asm volatile("" : "+v"(pk));
+#pragma unroll
+        for (int i = 0; i < kLdsRun; ++i)
+            if (i < len) {
+                sm[pk] = nw[i];
+                if (dl) sm[pk + dl] = nw[i];
+                if (dr) sm[pk + dr] = nw[i];
+                pk += P;
+            }
+        // the thread's own writes above are visible to its own reads
+        if (top_ghost >= 0) sm[top_ghost] = sm[base];
+        if (bot_ghost >= 0) sm[bot_ghost] = sm[base + (len - 1) * P];
+        __syncthreads();
+    }
+    for (int i = 0; i < len; ++i) {
+        const int r = r0 + i;
+        const float2 w = sm[base + i * P];
+        ou[r * C + c] = w.x;
+        ov[r * C + c] = w.y;
+    }
+}
+
+hipError_t launch_batch_lds(const BatchInst *insts, const int *ids, int count, int frame_cells,
+                            const float *in, float *out, int bc, long long T, hipStream_t s)
+{
+    const size_t bytes = sizeof(float2) * (size_t)frame_cells;
+    hipError_t e = hipFuncSetAttribute((const void *)batch_lds_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_lds_kernel, dim3((unsigned)count), dim3(kLdsThreads), bytes, s, insts,
+                       ids, in, out, bc, T);
+    return hipGetLastError();
+}
+
 namespace {
 
 using BatchFn = void (*)(BatchArgs);
@@ -121,6 +245,11 @@ struct TileTable {
 
 struct rdcnn_batch {
     int n, bc;
+    int use_lds;                // hold small instances in LDS for a whole run
+    int lds_limit;              // frame cells one workgroup's LDS can hold
+    std::vector<char> in_lds;   // instance i runs in the in-LDS kernel
+    int *lds_ids_dev;           // their indices
+    int lds_count, lds_frame;   // how many, largest frame
     std::vector<int> R, C;
     std::vector<long long> off;
     std::vector<rd::Gene> g;
@@ -156,6 +285,46 @@ void drop_graph(rdcnn_batch *b)
 
 // Defaults from a sweep of the 1024-instance parameter-sweep workload on MI355X
 // (two columns per lane, twelve steps per pass and 128-row tiles led).
+void free_lds(rdcnn_batch *b)
+{
+    if (b->lds_ids_dev) (void)hipFree(b->lds_ids_dev);
+    b->lds_ids_dev = nullptr;
+    b->lds_count = b->lds_frame = 0;
+    b->in_lds.assign(b->n, 0);
+}
+
+// Decide which instances the in-LDS kernel takes and upload their indices.
+int setup_lds(rdcnn_batch *b)
+{
+    free_lds(b);
+    if (!b->use_lds) return RDCNN_OK;
+    std::vector<int> ids;
+    int frame = 0;
+    for (int i = 0; i < b->n; ++i) {
+        const int R = b->R[i], C = b->C[i];
+        if (C > rd::kLdsThreads) continue;
+        const int runs = rd::kLdsThreads / C;
+        const int m = (R + runs - 1) / runs;
+        const long long fr = (long long)(runs * m + 2) * (C + 2);  // frame incl. unstored rows
+        if (m <= rd::kLdsRun && fr <= b->lds_limit) {
+            b->in_lds[i] = 1;
+            ids.push_back(i);
+            if (fr > frame) frame = (int)fr;
+        }
+    }
+    if (ids.empty()) return RDCNN_OK;
+    hipError_t e = hipMalloc((void **)&b->lds_ids_dev, sizeof(int) * ids.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(b->lds_ids_dev, ids.data(), sizeof(int) * ids.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_lds(b);
+        return bfail(RDCNN_ENOMEM, "batch: in-LDS table: %s", hipGetErrorString(e));
+    }
+    b->lds_count = (int)ids.size();
+    b->lds_frame = frame;
+    return RDCNN_OK;
+}
+
 void batch_config(const rdcnn_batch *b, int *cpl, int *depth, int *seg)
 {
     *cpl = b->cpl ? b->cpl : 2;
@@ -177,6 +346,7 @@ int table_for(rdcnn_batch *b, int cpl, int depth, int seg, const TileTable **out
     if (wout <= 0) return bfail(RDCNN_EINVAL, "batch: depth %d too large for cpl %d", depth, cpl);
     std::vector<rd::BatchTile> tiles;
     for (int i = 0; i < b->n; ++i) {
+        if (b->in_lds[i]) continue;
         const int R = b->R[i], C = b->C[i];
         const int h = seg < R ? seg : R;
         for (int sx = 0; sx * wout < C; ++sx)
@@ -190,6 +360,13 @@ int table_for(rdcnn_batch *b, int cpl, int depth, int seg, const TileTable **out
             }
     }
     if (tiles.size() >= (1u << 31)) return bfail(RDCNN_EINVAL, "batch: too many tiles");
+    if (tiles.empty()) {  // every instance runs in LDS
+        TileTable t;
+        t.depth = depth;
+        b->tables.push_back(t);
+        *out = &b->tables.back();
+        return RDCNN_OK;
+    }
     std::stable_sort(tiles.begin(), tiles.end(), [](const rd::BatchTile &a, const rd::BatchTile &c) {
         return (a.y1 - a.y0) > (c.y1 - c.y0);
     });
@@ -208,18 +385,30 @@ int table_for(rdcnn_batch *b, int cpl, int depth, int seg, const TileTable **out
     return RDCNN_OK;
 }
 
-// Enqueue the launches of T steps; cur flips once per launch.
+// Enqueue the launches of T steps; cur flips once per streamed launch.  The
+// in-LDS instances go first, in one launch, and write their final state to the
+// buffer that will be current after the T steps.
 int enqueue_steps(rdcnn_batch *b, long long T, int cpl, int depth, int seg)
 {
+    if (b->lds_count > 0 && T > 0) {
+        const long long passes = (T + depth - 1) / depth;
+        const int after = (passes % 2) ? 1 - b->cur : b->cur;
+        hipError_t e = rd::launch_batch_lds(b->insts_dev, b->lds_ids_dev, b->lds_count,
+                                            b->lds_frame, b->buf[b->cur], b->buf[after], b->bc,
+                                            T, b->stream);
+        if (e != hipSuccess) return bfail(RDCNN_EHIP, "batch: in-LDS launch: %s", hipGetErrorString(e));
+    }
     while (T > 0) {
         const int k = (int)(T < depth ? T : depth);
         const TileTable *t = nullptr;
         for (const TileTable &x : b->tables)
             if (x.depth == k) t = &x;
         if (!t) return bfail(RDCNN_ESTATE, "batch: missing tile table for depth %d", k);
-        hipError_t e = rd::launch_batch(t->dev, b->insts_dev, t->ntiles, b->buf[b->cur],
-                                        b->buf[1 - b->cur], b->bc, cpl, k, b->stream);
-        if (e != hipSuccess) return bfail(RDCNN_EHIP, "batch: launch: %s", hipGetErrorString(e));
+        if (t->ntiles > 0) {
+            hipError_t e = rd::launch_batch(t->dev, b->insts_dev, t->ntiles, b->buf[b->cur],
+                                            b->buf[1 - b->cur], b->bc, cpl, k, b->stream);
+            if (e != hipSuccess) return bfail(RDCNN_EHIP, "batch: launch: %s", hipGetErrorString(e));
+        }
         b->cur = 1 - b->cur;
         T -= k;
     }
@@ -301,6 +490,18 @@ int rdcnn_batch_create(rdcnn_batch_t *out, int n, const int *rows, const int *co
     b->graph = nullptr;
     b->graph_T = -1;
     b->graph_cur = b->graph_cpl = b->graph_depth = b->graph_seg = 0;
+    b->use_lds = 1;
+    b->lds_ids_dev = nullptr;
+    b->lds_count = b->lds_frame = 0;
+    b->in_lds.assign(n, 0);
+    {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+            b->lds_limit = lds / (int)sizeof(float2);
+        else
+            b->lds_limit = 0;
+    }
     hipError_t e = hipMalloc((void **)&b->insts_dev, sizeof(rd::BatchInst) * n);
     if (e != hipSuccess) {
         delete b;
@@ -315,8 +516,30 @@ int rdcnn_batch_create(rdcnn_batch_t *out, int n, const int *rows, const int *co
         delete b;
         return bfail(RDCNN_EHIP, "rdcnn_batch_create: %s", hipGetErrorString(e));
     }
+    int rc = setup_lds(b);
+    if (rc != RDCNN_OK) {
+        (void)hipFree(b->insts_dev);
+        delete b;
+        return rc;
+    }
     *out = b;
     return RDCNN_OK;
+}
+
+int rdcnn_batch_lds_instances(rdcnn_batch_t b, int *count)
+{
+    if (!b || !count) return bfail(RDCNN_EINVAL, "rdcnn_batch_lds_instances: NULL argument");
+    *count = b->lds_count;
+    return RDCNN_OK;
+}
+
+int rdcnn_batch_use_lds(rdcnn_batch_t b, int on)
+{
+    if (!b) return bfail(RDCNN_EINVAL, "rdcnn_batch_use_lds: NULL handle");
+    b->use_lds = on ? 1 : 0;
+    free_tables(b);
+    drop_graph(b);
+    return setup_lds(b);
 }
 
 int rdcnn_batch_set_kernel(rdcnn_batch_t b, int depth, int cols_per_lane, int seg_rows)
@@ -406,6 +629,7 @@ int rdcnn_batch_destroy(rdcnn_batch_t b)
     if (!b) return RDCNN_OK;
     drop_graph(b);
     free_tables(b);
+    free_lds(b);
     if (b->insts_dev) (void)hipFree(b->insts_dev);
     delete b;
     return RDCNN_OK;

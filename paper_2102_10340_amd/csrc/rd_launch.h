@@ -84,6 +84,11 @@ struct BatchInst;
 hipError_t launch_batch(const BatchTile *tiles, const BatchInst *insts, int ntiles,
                         const float *in, float *out, int bc, int cpl, int depth, hipStream_t s);
 
+// All T steps of `count` small instances (indices ids), each held in one
+// workgroup's LDS (frame_cells = largest (R+2)*(C+2)).
+hipError_t launch_batch_lds(const BatchInst *insts, const int *ids, int count, int frame_cells,
+                            const float *in, float *out, int bc, long long T, hipStream_t s);
+
 // gx = ka (lam + mu) over n cells.
 hipError_t launch_init_backward(const float *adj, long long n, float ka, float *gx,
                                 hipStream_t s);
