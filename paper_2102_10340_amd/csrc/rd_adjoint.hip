@@ -41,12 +41,14 @@ struct AdjArgs {
 };
 
 // LAMS: also sum the three lam-weighted products only dJ/ddt, dJ/dc and dJ/dk3
-// need (S_LU, S_LU3, S_LV).
-template <int CPL, int KB, bool FAST, bool LAMS>
+// need (S_LU, S_LU3, S_LV).  ROWS_IN: every row the tile reads lies inside the
+// grid, so row offsets need no boundary mapping.
+template <int CPL, int KB, bool FAST, bool ROWS_IN, bool LAMS>
 __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &t)
 {
     const int C = A.t.C, R = A.t.R, bc = A.t.bc;
     const unsigned pbytes = 4u * (unsigned)R * (unsigned)C;
+    const unsigned rowb = 4u * (unsigned)C;
     const Buf il(A.in, pbytes), im(A.in + (size_t)R * C, pbytes);
     const Buf ol(A.out, pbytes), om(A.out + (size_t)R * C, pbytes);
     const Buf sb(A.states, 2u * (unsigned)KB * pbytes);
@@ -57,6 +59,10 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &
     const int rbase = y0 - KB;
     const int n_real = y1 - y0 + 2 * KB;
     const int n_iter = (n_real + 2) / 3 * 3;
+    // Byte offset of row r (rows outside the grid only occur with ROWS_IN false).
+    auto roff = [&](int r) -> unsigned {
+        return ROWS_IN ? (unsigned)r * rowb : row_off(r, R, C, bc);
+    };
 
     // 1 for this lane's output cells, 0 for halo cells.  In full-width tiles a
     // lane's columns are all output or all halo, so its sums are weighted once
@@ -83,7 +89,7 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &
             sv[j][0][e] = sv[j][1][e] = sv[j][2][e] = 0.0f;
         }
     {
-        const unsigned ro = row_off(rbase, R, C, bc);
+        const unsigned ro = roff(rbase);
         load_row<CPL, FAST>(il, ro, t, bl[0][0]);
         load_row<CPL, FAST>(im, ro, t, bm[0][0]);
     }
@@ -101,7 +107,8 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &
                 const float rl = from_right_lane(bl[i][sl.cs][0]);
                 const float lm = from_left_lane(bm[i][sl.cs][CPL - 1]);
                 const float rm = from_right_lane(bm[i][sl.cs][0]);
-                const bool count = m >= y0 && m < y1;
+                // uniform; readfirstlane keeps the branch on the scalar unit
+                const int count = __builtin_amdgcn_readfirstlane((int)(m >= y0 && m < y1));
 #pragma unroll
                 for (int e = 0; e < CPL; ++e) {
                     const float l = bl[i][sl.cs][e], mu = bm[i][sl.cs][e];
@@ -109,10 +116,13 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &
                     const float lE = e == CPL - 1 ? rl : bl[i][sl.cs][e + 1];
                     const float mW = e == 0 ? lm : bm[i][sl.cs][e - 1];
                     const float mE = e == CPL - 1 ? rm : bm[i][sl.cs][e + 1];
-                    const float Ll = __builtin_fmaf(
-                        -4.0f, l, (bl[i][sl.ps][e] + bl[i][sl.ns][e]) + (lW + lE));
-                    const float Lm = __builtin_fmaf(
-                        -4.0f, mu, (bm[i][sl.ps][e] + bm[i][sl.ns][e]) + (mW + mE));
+                    // the lane-shifted neighbour first, so its shift folds into
+                    // the add (a + b == b + a exactly)
+                    const bool sw = CPL > 1 && e == CPL - 1;
+                    const float sl_ = sw ? lE + lW : lW + lE;
+                    const float sm_ = sw ? mE + mW : mW + mE;
+                    const float Ll = __builtin_fmaf(-4.0f, l, (bl[i][sl.ps][e] + bl[i][sl.ns][e]) + sl_);
+                    const float Lm = __builtin_fmaf(-4.0f, mu, (bm[i][sl.ps][e] + bm[i][sl.ns][e]) + sm_);
                     const float u = su[i][sl.cs][e], v = sv[i][sl.cs][e];
                     const float u2 = u * u;
                     const float gl = __builtin_fmaf(-c3k, u2, g.c) * l;
@@ -138,18 +148,20 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &
                     }
                 }
             }
-            // The state row this level needs two iterations on (level i works
-            // from it = 2i+2 to n_real-1); level i reads state KB-1-i.  Its slot
-            // held the row used one iteration ago.
-            if (it + 2 >= 2 * i + 2 && it + 2 < n_real) {
-                const unsigned o = 2u * (unsigned)(KB - 1 - i) * pbytes + row_off(m + 2, R, C, bc);
-                load_row<CPL, FAST>(sb, o, t, su[i][sl.ps]);
-                load_row<CPL, FAST>(sb, o + pbytes, t, sv[i][sl.ps]);
-            }
+            // Loads in the order they are needed (vmcnt retires in issue
+            // order): the level-0 row for the next iteration ...
             if (i == 0) {
-                const unsigned ro = row_off(rbase + it + 1, R, C, bc);
+                const unsigned ro = roff(rbase + it + 1);
                 load_row<CPL, FAST>(il, ro, t, bl[0][sl.ps]);
                 load_row<CPL, FAST>(im, ro, t, bm[0][sl.ps]);
+            }
+            // ... then the state row this level needs two iterations on (level
+            // i works from it = 2i+2 to n_real-1 and reads state KB-1-i); its
+            // slot held the row used one iteration ago.
+            if (it + 2 >= 2 * i + 2 && it + 2 < n_real) {
+                const unsigned o = 2u * (unsigned)(KB - 1 - i) * pbytes + roff(m + 2);
+                load_row<CPL, FAST>(sb, o, t, su[i][sl.ps]);
+                load_row<CPL, FAST>(sb, o + pbytes, t, sv[i][sl.ps]);
             }
         }
         const int m = rbase + it - KB;
@@ -182,10 +194,14 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs A)
 {
     Tile<CPL> t;
     if (!t.init(A.t)) return;
-    if (t.fast)
-        adjoint_body<CPL, KB, true, LAMS>(A, t);
-    else
-        adjoint_body<CPL, KB, false, LAMS>(A, t);
+    if (t.fast) {
+        if (t.y0 >= KB && t.y1 + KB <= A.t.R)
+            adjoint_body<CPL, KB, true, true, LAMS>(A, t);
+        else
+            adjoint_body<CPL, KB, true, false, LAMS>(A, t);
+    } else {
+        adjoint_body<CPL, KB, false, false, LAMS>(A, t);
+    }
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(double *p, long long n)

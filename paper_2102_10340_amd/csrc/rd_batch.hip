@@ -65,10 +65,14 @@ __global__ __launch_bounds__(64) void batch_step_kernel(BatchArgs B)
     A.rec = nullptr;
     Tile<CPL> t;
     t.setup(A.t, id, bt.x0, bt.y0, bt.y1);
-    if (t.fast)
-        stream_body<CPL, K, false, true>(A, t);
-    else
-        stream_body<CPL, K, false, false>(A, t);
+    if (t.fast) {
+        if (t.y0 >= K && t.y1 + K <= in.R)
+            stream_body<CPL, K, false, true, true>(A, t);
+        else
+            stream_body<CPL, K, false, true, false>(A, t);
+    } else {
+        stream_body<CPL, K, false, false, false>(A, t);
+    }
 }
 
 // ---------------------------------------------------------------- in-LDS instances

@@ -62,18 +62,21 @@ __device__ __forceinline__ int map_index(int i, int n, int bc)
     return i;
 }
 
-// Lane i receives lane i-1's value (lane 0 receives 0): DPP wave_shr:1.
+// Lane i receives lane i-1's value (lane 0 receives 0): DPP wave_shr:1.  With
+// bound_ctrl set, a lane with no source lane reads 0 directly, so the compiler
+// needs no zeroed destination register first and can fold the shift into the
+// add that consumes it.
 __device__ __forceinline__ float from_left_lane(float x)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
-                                                                 0x138, 0xF, 0xF, false));
+                                                                 0x138, 0xF, 0xF, true));
 }
 
 // Lane i receives lane i+1's value (lane 63 receives 0): DPP wave_shl:1.
 __device__ __forceinline__ float from_right_lane(float x)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
-                                                                 0x130, 0xF, 0xF, false));
+                                                                 0x130, 0xF, 0xF, true));
 }
 
 // Workgroups are handed to the 8 XCDs round-robin; renumber them so that each

@@ -89,10 +89,14 @@ __global__ __launch_bounds__(64) void stream_step_kernel(StreamArgs A)
 {
     Tile<CPL> t;
     if (!t.init(A.t)) return;
-    if (t.fast)
-        stream_body<CPL, K, REC, true>(A, t);
-    else
-        stream_body<CPL, K, REC, false>(A, t);
+    if (t.fast) {
+        if (t.y0 >= K && t.y1 + K <= A.t.R)
+            stream_body<CPL, K, REC, true, true>(A, t);
+        else
+            stream_body<CPL, K, REC, true, false>(A, t);
+    } else {
+        stream_body<CPL, K, REC, false, false>(A, t);
+    }
 }
 
 bool stream_geometry(int R, int C, int cpl, int depth, int seg_rows, StreamGeom *g)

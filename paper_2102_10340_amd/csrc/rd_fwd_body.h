@@ -20,11 +20,14 @@ struct StreamArgs {
     float *rec;  // recording: level j of the pass goes to state j of rec (null: off)
 };
 
-template <int CPL, int K, bool REC, bool FAST>
+// ROWS_IN: every row the tile reads lies inside the grid, so row offsets need
+// no boundary mapping (true for all but the first and last segment of a strip).
+template <int CPL, int K, bool REC, bool FAST, bool ROWS_IN>
 __device__ __forceinline__ void stream_body(const StreamArgs &A, const Tile<CPL> &t)
 {
     const int C = A.t.C, R = A.t.R, bc = A.t.bc;
     const unsigned pbytes = 4u * (unsigned)R * (unsigned)C;  // one plane
+    const unsigned rowb = 4u * (unsigned)C;
     const Buf iu(A.in, pbytes), iv(A.in + (size_t)R * C, pbytes);
     const Buf ou(A.out, pbytes), ov(A.out + (size_t)R * C, pbytes);
     // K recorded states, u plane then v plane each: state j at byte 2*j*pbytes.
@@ -35,6 +38,9 @@ __device__ __forceinline__ void stream_body(const StreamArgs &A, const Tile<CPL>
     const int rbase = y0 - K;                 // first row read (level 0)
     const int n_real = y1 - y0 + 2 * K;       // rows walked
     const int n_iter = (n_real + 2) / 3 * 3;  // ... padded to a multiple of 3
+    auto roff = [&](int r) -> unsigned {
+        return ROWS_IN ? (unsigned)r * rowb : row_off(r, R, C, bc);
+    };
 
     // Row q (counted from rbase) of time level j lives in slot q % 3 of level
     // j.  Iteration `it` reads level-0 row it and makes level-(j+1) row it-j-1
@@ -50,7 +56,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs &A, const Tile<CPL>
 #pragma unroll
             for (int e = 0; e < CPL; ++e) bu[j][q][e] = bv[j][q][e] = 0.0f;
     {
-        const unsigned ro = row_off(rbase, R, C, bc);
+        const unsigned ro = roff(rbase);
         load_row<CPL, FAST>(iu, ro, t, bu[0][0]);
         load_row<CPL, FAST>(iv, ro, t, bv[0][0]);
     }
@@ -75,20 +81,27 @@ __device__ __forceinline__ void stream_body(const StreamArgs &A, const Tile<CPL>
                     const float uE = e == CPL - 1 ? ru : bu[j][sl.cs][e + 1];
                     const float vW = e == 0 ? lv : bv[j][sl.cs][e - 1];
                     const float vE = e == CPL - 1 ? rv : bv[j][sl.cs][e + 1];
-                    cell_update(g, bu[j][sl.cs][e], bv[j][sl.cs][e], bu[j][sl.ps][e],
-                                bu[j][sl.ns][e], uW, uE, bv[j][sl.ps][e], bv[j][sl.ns][e], vW, vE,
-                                du[e], dv[e]);
-                }
-                if (REC && j + 1 < K) {
-                    const int m = rbase + it - j - 1;
-                    if (m >= y0 && m < y1) {
-                        const unsigned o = 2u * (unsigned)(j + 1) * pbytes + 4u * (unsigned)m * C;
-                        store_row<CPL, FAST>(rb, o, C, t, bu[j + 1][sl.cs]);
-                        store_row<CPL, FAST>(rb, o + pbytes, C, t, bv[j + 1][sl.cs]);
-                    }
+                    // The lane-shifted neighbour goes first in its add so the
+                    // compiler can fold the shift into it (a + b == b + a
+                    // exactly, so the result does not change).
+                    if (CPL > 1 && e == CPL - 1)
+                        cell_update(g, bu[j][sl.cs][e], bv[j][sl.cs][e], bu[j][sl.ps][e],
+                                    bu[j][sl.ns][e], uE, uW, bv[j][sl.ps][e], bv[j][sl.ns][e], vE,
+                                    vW, du[e], dv[e]);
+                    else
+                        cell_update(g, bu[j][sl.cs][e], bv[j][sl.cs][e], bu[j][sl.ps][e],
+                                    bu[j][sl.ns][e], uW, uE, bv[j][sl.ps][e], bv[j][sl.ns][e], vW,
+                                    vE, du[e], dv[e]);
                 }
             }
+            // The next level-0 row is loaded before this iteration's stores:
+            // vmcnt retires in issue order, so waiting for the load next
+            // iteration then does not also wait for the stores.
             if (j == 0) {
+                // Level-0 row it-2 is spent: fetch row it+1 into its slot.
+                const unsigned ro = roff(rbase + it + 1);
+                load_row<CPL, FAST>(iu, ro, t, bu[0][sl.ps]);
+                load_row<CPL, FAST>(iv, ro, t, bv[0][sl.ps]);
                 if (REC) {
                     const int m = rbase + it;  // level-0 row it
                     if (m >= y0 && m < y1) {
@@ -97,10 +110,14 @@ __device__ __forceinline__ void stream_body(const StreamArgs &A, const Tile<CPL>
                         store_row<CPL, FAST>(rb, o + pbytes, C, t, bv[0][sl.ns]);
                     }
                 }
-                // Level-0 row it-2 is spent: fetch row it+1 into its slot.
-                const unsigned ro = row_off(rbase + it + 1, R, C, bc);
-                load_row<CPL, FAST>(iu, ro, t, bu[0][sl.ps]);
-                load_row<CPL, FAST>(iv, ro, t, bv[0][sl.ps]);
+            }
+            if (REC && j + 1 < K && it >= 2 * j + 2 && it < n_real) {
+                const int m = rbase + it - j - 1;  // level-(j+1) row just made
+                if (m >= y0 && m < y1) {
+                    const unsigned o = 2u * (unsigned)(j + 1) * pbytes + 4u * (unsigned)m * C;
+                    store_row<CPL, FAST>(rb, o, C, t, bu[j + 1][sl.cs]);
+                    store_row<CPL, FAST>(rb, o + pbytes, C, t, bv[j + 1][sl.cs]);
+                }
             }
         }
         const int m = rbase + it - K;  // row of level K now in (tu, tv)
