@@ -15,12 +15,16 @@ with gcc); this module only marshals numpy arrays.  What is computed:
 * :func:`grad` -- reverse pass of Eq. (1)-(3): dJ/ds_0 and dJ/dp for a loss
   J(s_T), by checkpoint-and-recompute.
 
+The per-instance statistics of a parameter atlas (Sec. III.A) are plain
+definitions written out in numpy in :mod:`oracle.atlas`.
+
 Parameters are given as a mapping with keys ``dt, a, b, eps, c, k3, Du, Dv``
 (the paper's gene, Sec. II.A, plus the cubic coefficient k3 of Eq. (2), which
 the paper fixes at 1/3).  Boundary rule: ``"periodic"`` (toroidal, as in the
 paper's kernels) or ``"zeroflux"`` (ghost cell copies the edge cell).
 
 Parity status: every function here is pinned by ``tests/test_oracle_pins.py``
+and ``tests/test_atlas_pins.py``
 (closed forms, invariants, brute force, library routines, hand-worked golden
 values and finite differences); none is "parity unpinned".
 """
