@@ -49,8 +49,8 @@ def parse():
                     help="first run a plain device copy of this size (scales HBM counters)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the differentiation and parameter-sweep workloads")
-    ap.add_argument("--only-extra", choices=["fwd_bwd", "batched", "small_batch", "plain", "edge",
-                                                   "table1"],
+    ap.add_argument("--only-extra", choices=["fwd_bwd", "batched", "small_batch", "atlas", "plain",
+                                                   "edge", "table1"],
                     help="run just this extra workload after the forward steps (profiling)")
     return ap.parse_args()
 
@@ -208,6 +208,49 @@ def bench_small_batch(stream, per_instance_sample=8):
             "per_instance_s_est": t_one, "lds_vs_streamed": t_st / t_lds,
             "lds_vs_per_instance": t_one / t_lds, "lds_equals_streamed_bitwise": same,
             "baseline_sample": f"{per_instance_sample} instances run alone, scaled by 1024"}
+
+
+def bench_atlas(stream):
+    """Parameter atlas after Sec. III.A: (Du, Dv) on a 32 x 32 grid (Du = 0.025 ..
+    0.8, Dv = 0.05 .. 1.6), the paper's default gene, periodic, 256x256 with the
+    random 11x11 centre patch, T = 10^4 steps in one batch; per-instance
+    statistics at T - 10^3 and T on the GPU, one class per point on the host.
+    Reports the whole scan's rate and the statistics kernels' HBM rate (12 B per
+    cell read with the earlier state, 8 B without)."""
+    import numpy as np
+    import torch
+    from paper_2102_10340_amd import Batch, atlas
+    T, dT, N = 10000, 1000, 256
+    du = 0.025 * np.arange(1, 33)
+    dv = 0.05 * np.arange(1, 33)
+    g = W.gene(W.PAPER_DEFAULT_GENE)
+    genes = [dict(g, Du=float(a), Dv=float(b)) for a in du for b in dv]
+    x = torch.from_numpy(W.centre_patch_x(N, N, 11, 0)).cuda()
+    b = Batch([x] * len(genes), genes, "periodic")
+    ref = torch.tensor([atlas.rest_state(q)[0] for q in genes], dtype=torch.float32, device="cuda")
+    out = {}
+
+    def run():
+        b.step(T - dT)
+        out["prev"] = b.snapshot()
+        out["s0"] = b.stats(None, ref, 0.05, 1e-3)
+        b.step(dT)
+        out["s1"] = b.stats(out["prev"], ref, 0.05, 1e-3)
+
+    t_scan = _timed(run, stream)
+    cells = len(genes) * N * N
+    t_stats = _timed(lambda: [b.stats(out["prev"], ref, 0.05, 1e-3) for _ in range(10)], stream) / 10
+    cls = atlas.classify(out["s0"].cpu().numpy(), out["s1"].cpu().numpy()).reshape(32, 32)
+    b.close()
+    named = {}
+    for (a, c) in ((0.3, 1.0), (0.5, 0.8), (0.7, 0.8)):
+        named[f"{a},{c}"] = atlas.CLASSES[cls[int(round(a / 0.025)) - 1, int(round(c / 0.05)) - 1]]
+    return {"workload": "32x32 (Du,Dv) scan, 256x256 periodic, paper gene, 11x11 patch, T=10000, "
+                        "stats at T-1000 and T",
+            "scan_gcells": cells * T / t_scan / 1e9, "scan_s": t_scan,
+            "stats_ms": t_stats * 1e3, "stats_gbs": 12 * cells / t_stats / 1e9,
+            "classes": {atlas.CLASSES[k]: int((cls == k).sum()) for k in range(4)},
+            "paper_points": named}
 
 
 def bench_plain(stream):
@@ -415,6 +458,8 @@ def main():
                 out["batched"] = bench_batched(stream)
             if args.only_extra in (None, "small_batch"):
                 out["small_batch"] = bench_small_batch(stream)
+            if args.only_extra in (None, "atlas"):
+                out["atlas"] = bench_atlas(stream)
             if args.only_extra in (None, "plain"):
                 out["plain"] = bench_plain(stream)
             if args.only_extra in (None, "edge"):

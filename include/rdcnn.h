@@ -245,6 +245,27 @@ int rdcnn_batch_use_lds(rdcnn_batch_t b, int on);
  * kernel runs under the current setting.  Errors: RDCNN_EINVAL (NULL). */
 int rdcnn_batch_lds_instances(rdcnn_batch_t b, int *count);
 
+/*
+ * rdcnn_batch_stats -- per-instance statistics of the current state for a
+ * parameter atlas (the automated form of the (Du, Dv) scans of Sec. III.A,
+ * Fig. 9).  For instance i with N cells, out[8*i + k] (doubles, device) is
+ *   0 mean_u   1 var_u   2 mean_v   3 var_v
+ *   4 frac_far    = #{ |u - ref[i]| > theta_far } / N
+ *   5 frac_moving = #{ |u - u_prev| > theta_move } / N
+ *   6 max_change  = max |u - u_prev|
+ *   7 rms_change  = sqrt(sum (u - u_prev)^2 / N)
+ * where u_prev comes from `prev` (device, a packed buffer in this batch's
+ * layout holding an earlier state, e.g. a copy of rdcnn_batch_current's
+ * buffer; 16-byte aligned); with prev NULL entries 5-7 are NaN.  ref: device array of n floats,
+ * or NULL for 0.  Threshold tests and differences are taken in float32 (exact
+ * counts); sums in double, folded in a fixed order (deterministic).  The first
+ * call allocates a chunk table and partial buffer kept until destroy.
+ * Stream-ordered on the batch's stream.  Errors: RDCNN_EINVAL (NULL b or out,
+ * thresholds negative or not finite, prev misaligned), RDCNN_ENOMEM, RDCNN_EHIP.
+ */
+int rdcnn_batch_stats(rdcnn_batch_t b, const float *prev, const float *ref, float theta_far,
+                      float theta_move, double *out);
+
 /* rdcnn_batch_destroy -- release the batch (not the caller's buffers).  NULL is a no-op. */
 int rdcnn_batch_destroy(rdcnn_batch_t b);
 

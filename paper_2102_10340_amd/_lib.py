@@ -63,6 +63,7 @@ _SIGS = {
     "rdcnn_batch_use_graph": [_P, _I],
     "rdcnn_batch_use_lds": [_P, _I],
     "rdcnn_batch_lds_instances": [_P, ctypes.POINTER(ctypes.c_int)],
+    "rdcnn_batch_stats": [_P, _P, _P, _F, _F, _P],
     "rdcnn_batch_destroy": [_P],
 }
 for _name, _args in _SIGS.items():

@@ -84,6 +84,32 @@ class Batch:
                 return b
         raise RuntimeError("current buffer not found")
 
+    def snapshot(self) -> torch.Tensor:
+        """A copy of the current packed state (for the change statistics)."""
+        return self.current().clone()
+
+    STAT_NAMES = ("mean_u", "var_u", "mean_v", "var_v", "frac_far", "frac_moving",
+                  "max_change", "rms_change")
+
+    def stats(self, prev: torch.Tensor = None, ref=None, theta_far: float = 0.0,
+              theta_move: float = 0.0) -> torch.Tensor:
+        """Per-instance statistics of the current state, [n, 8] float64 on the
+        device (columns STAT_NAMES; rdcnn_batch_stats).  prev: an earlier
+        snapshot(); ref: per-instance reference value of u (sequence or tensor)."""
+        out = torch.empty((len(self), 8), dtype=torch.float64, device=self.device)
+        if prev is not None and (prev.dtype != torch.float32 or prev.numel() < self.total
+                                 or prev.device != self.device):
+            raise ValueError("prev must be a float32 snapshot() of this batch")
+        r = None
+        if ref is not None:
+            r = torch.as_tensor(ref, dtype=torch.float32, device=self.device).reshape(-1).contiguous()
+            if r.numel() != len(self):
+                raise ValueError("ref needs one value per instance")
+        check(lib.rdcnn_batch_stats(self._h, None if prev is None else prev.data_ptr(),
+                                    None if r is None else r.data_ptr(), float(theta_far),
+                                    float(theta_move), out.data_ptr()))
+        return out
+
     def state(self, i: int) -> torch.Tensor:
         """View [2, R, C] (u, v) of instance i in the current buffer."""
         R, C = self.shapes[i]

@@ -22,12 +22,6 @@
 
 namespace rd {
 
-struct BatchInst {
-    long long off;  // float offset of the instance in a packed buffer
-    int R, C;
-    Gene g;
-};
-
 struct BatchTile {
     int inst, x0, y0, y1;
 };
@@ -267,6 +261,12 @@ struct rdcnn_batch {
     hipGraphExec_t graph;
     long long graph_T;
     int graph_cur, graph_cpl, graph_depth, graph_seg;
+    // atlas statistics: chunk list, per-instance chunk ranges, partials (made
+    // on the first rdcnn_batch_stats call)
+    rd::StatChunk *stat_chunks;
+    int *stat_first;
+    double *stat_partial;
+    int stat_nchunks;
 };
 
 #define bfail(...) rd::set_error(__VA_ARGS__)
@@ -289,6 +289,51 @@ void drop_graph(rdcnn_batch *b)
 
 // Defaults from a sweep of the 1024-instance parameter-sweep workload on MI355X
 // (two columns per lane, twelve steps per pass and 128-row tiles led).
+void free_stats(rdcnn_batch *b)
+{
+    if (b->stat_chunks) (void)hipFree(b->stat_chunks);
+    if (b->stat_first) (void)hipFree(b->stat_first);
+    if (b->stat_partial) (void)hipFree(b->stat_partial);
+    b->stat_chunks = nullptr;
+    b->stat_first = nullptr;
+    b->stat_partial = nullptr;
+    b->stat_nchunks = 0;
+}
+
+int setup_stats(rdcnn_batch *b)
+{
+    std::vector<rd::StatChunk> ch;
+    std::vector<int> first(b->n + 1);
+    for (int i = 0; i < b->n; ++i) {
+        first[i] = (int)ch.size();
+        const long long cells = (long long)b->R[i] * b->C[i];
+        for (long long s = 0; s < cells; s += rd::kStatChunk) {
+            rd::StatChunk c;
+            c.inst = i;
+            c.start = (int)s;
+            c.count = (int)(cells - s < rd::kStatChunk ? cells - s : rd::kStatChunk);
+            ch.push_back(c);
+        }
+    }
+    first[b->n] = (int)ch.size();
+    if (ch.size() >= (1u << 31)) return bfail(RDCNN_EINVAL, "rdcnn_batch_stats: too many chunks");
+    hipError_t e = hipMalloc((void **)&b->stat_chunks, sizeof(rd::StatChunk) * ch.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&b->stat_first, sizeof(int) * first.size());
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&b->stat_partial, sizeof(double) * rd::kStats * ch.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(b->stat_chunks, ch.data(), sizeof(rd::StatChunk) * ch.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->stat_first, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_stats(b);
+        return bfail(RDCNN_ENOMEM, "rdcnn_batch_stats: %s", hipGetErrorString(e));
+    }
+    b->stat_nchunks = (int)ch.size();
+    return RDCNN_OK;
+}
+
 void free_lds(rdcnn_batch *b)
 {
     if (b->lds_ids_dev) (void)hipFree(b->lds_ids_dev);
@@ -494,6 +539,10 @@ int rdcnn_batch_create(rdcnn_batch_t *out, int n, const int *rows, const int *co
     b->graph = nullptr;
     b->graph_T = -1;
     b->graph_cur = b->graph_cpl = b->graph_depth = b->graph_seg = 0;
+    b->stat_chunks = nullptr;
+    b->stat_first = nullptr;
+    b->stat_partial = nullptr;
+    b->stat_nchunks = 0;
     b->use_lds = 1;
     b->lds_ids_dev = nullptr;
     b->lds_count = b->lds_frame = 0;
@@ -527,6 +576,26 @@ int rdcnn_batch_create(rdcnn_batch_t *out, int n, const int *rows, const int *co
         return rc;
     }
     *out = b;
+    return RDCNN_OK;
+}
+
+int rdcnn_batch_stats(rdcnn_batch_t b, const float *prev, const float *ref, float theta_far,
+                      float theta_move, double *out)
+{
+    if (!b || !out) return bfail(RDCNN_EINVAL, "rdcnn_batch_stats: NULL argument");
+    if (!(theta_far >= 0.0f) || !(theta_move >= 0.0f) || !isfinite(theta_far) ||
+        !isfinite(theta_move))
+        return bfail(RDCNN_EINVAL, "rdcnn_batch_stats: thresholds must be finite and >= 0");
+    if ((uintptr_t)prev % 16 != 0)
+        return bfail(RDCNN_EINVAL, "rdcnn_batch_stats: prev must be 16-byte aligned");
+    if (!b->stat_chunks) {
+        const int rc = setup_stats(b);
+        if (rc != RDCNN_OK) return rc;
+    }
+    hipError_t e = rd::launch_stats(b->insts_dev, b->stat_chunks, b->stat_nchunks, b->stat_first,
+                                    b->n, b->buf[b->cur], prev, ref, theta_far, theta_move,
+                                    b->stat_partial, out, b->stream);
+    if (e != hipSuccess) return bfail(RDCNN_EHIP, "rdcnn_batch_stats: %s", hipGetErrorString(e));
     return RDCNN_OK;
 }
 
@@ -634,6 +703,7 @@ int rdcnn_batch_destroy(rdcnn_batch_t b)
     drop_graph(b);
     free_tables(b);
     free_lds(b);
+    free_stats(b);
     if (b->insts_dev) (void)hipFree(b->insts_dev);
     delete b;
     return RDCNN_OK;

@@ -78,9 +78,15 @@ hipError_t launch_zero(double *p, long long n, hipStream_t s);
 hipError_t launch_adjoint_finish(const double *partial, int ntiles, const Gene &g, unsigned mask,
                                  double *dtheta, hipStream_t s);
 
+// One instance of a batch: its offset in the packed buffers, size and gene.
+struct BatchInst {
+    long long off;  // float offset of the instance in a packed buffer
+    int R, C;
+    Gene g;
+};
+
 // One launch of the batched kernel: `depth` steps for every tile of the list.
 struct BatchTile;
-struct BatchInst;
 hipError_t launch_batch(const BatchTile *tiles, const BatchInst *insts, int ntiles,
                         const float *in, float *out, int bc, int cpl, int depth, hipStream_t s);
 
@@ -88,6 +94,21 @@ hipError_t launch_batch(const BatchTile *tiles, const BatchInst *insts, int ntil
 // workgroup's LDS (frame_cells = largest (R+2)*(C+2)).
 hipError_t launch_batch_lds(const BatchInst *insts, const int *ids, int count, int frame_cells,
                             const float *in, float *out, int bc, long long T, hipStream_t s);
+
+// Per-instance atlas statistics: chunks of at most kStatChunk cells, one
+// workgroup each, folded per instance in chunk order (first[i] .. first[i+1]).
+constexpr int kStats = 8;
+constexpr int kStatThreads = 256;
+constexpr int kStatChunk = 16384;
+struct StatChunk {
+    int inst;   // instance
+    int start;  // first cell (within the instance's plane)
+    int count;  // cells
+};
+hipError_t launch_stats(const BatchInst *insts, const StatChunk *chunks, int nchunks,
+                        const int *first, int n_inst, const float *cur, const float *prev,
+                        const float *ref, float theta_far, float theta_move, double *partial,
+                        double *out, hipStream_t s);
 
 // gx = ka (lam + mu) over n cells.
 hipError_t launch_init_backward(const float *adj, long long n, float ka, float *gx,

@@ -77,6 +77,9 @@ def test_null_handle_calls_fail_cleanly(L):
     assert L.lib.rdcnn_current(None, None) == L.EINVAL
     assert L.lib.rdcnn_set_kernel(None, 0, 0, 0, 0) == L.EINVAL
     assert L.lib.rdcnn_destroy(None) == L.OK
+    assert L.lib.rdcnn_batch_stats(None, None, None, 0.0, 0.0, 0x1000) == L.EINVAL
+    assert L.lib.rdcnn_batch_use_lds(None, 1) == L.EINVAL
+    assert L.lib.rdcnn_batch_lds_instances(None, None) == L.EINVAL
     assert "NULL" in L.last_error()
 
 
