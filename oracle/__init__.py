@@ -15,6 +15,11 @@ with gcc); this module only marshals numpy arrays.  What is computed:
 * :func:`grad` -- reverse pass of Eq. (1)-(3): dJ/ds_0 and dJ/dp for a loss
   J(s_T), by checkpoint-and-recompute.
 
+Two further cell models on the same grid and boundary rules (``cell_models.c``,
+after the extension to other finite-difference and cellular models that Sec. IV
+names): :func:`gs_run` (Gray-Scott reaction-diffusion) and :func:`cnn_input` /
+:func:`cnn_run` (a Chua-Yang cellular neural network with 3x3 templates).
+
 The per-instance statistics of a parameter atlas (Sec. III.A) are plain
 definitions written out in numpy in :mod:`oracle.atlas`.
 
@@ -38,6 +43,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rdcnn_oracle.c")
+_SRC_MODELS = os.path.join(_HERE, "cell_models.c")
 _LIB = os.path.join(_HERE, "liboracle_rdcnn.so")
 
 PARAM_ORDER = ("dt", "a", "b", "eps", "c", "k3", "Du", "Dv")
@@ -49,7 +55,7 @@ _lib = None
 def build(verbose: bool = False) -> str:
     """Compile the oracle with gcc (no fast-math, no FMA contraction, OpenMP rows)."""
     cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-           "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+           "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, _SRC_MODELS, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
@@ -61,7 +67,8 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                                                os.path.getmtime(_SRC_MODELS)):
         build()
     lib = ctypes.CDLL(_LIB)
     L, I, P = ctypes.c_long, ctypes.c_int, ctypes.c_void_p
@@ -71,6 +78,12 @@ def _load():
     lib.oracle_grad.argtypes = [L, L, I, P, I, P, P, L, L, P, P, P, P, P]
     for f in (lib.oracle_run_f32, lib.oracle_run_f64, lib.oracle_laplacian_f64, lib.oracle_grad):
         f.restype = ctypes.c_int
+    lib.oracle_gs_run.argtypes = [L, L, I, I, P, L, P, P]
+    lib.oracle_gs_run.restype = ctypes.c_int
+    lib.oracle_cnn_input.argtypes = [L, L, I, I, P, P, P]
+    lib.oracle_cnn_input.restype = None
+    lib.oracle_cnn_run.argtypes = [L, L, I, I, P, L, P, P]
+    lib.oracle_cnn_run.restype = ctypes.c_int
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -175,3 +188,45 @@ def grad(u0, v0, params, bc, T, lamT, muT, traj="f32", S=None):
     if rc != 0:
         raise ValueError("oracle grad rejected its arguments")
     return lam, mu, dict(zip(PARAM_ORDER, g.tolist())), uT, vT
+
+
+GS_ORDER = ("dt", "F", "k", "Du", "Dv")
+
+
+def _prec(precision):
+    return (64, np.float64) if precision == "f64" else (32, np.float32)
+
+
+def gs_run(u0, v0, params, bc: str, T: int, precision: str = "f32"):
+    """T Gray-Scott steps (cell_models.c): params maps dt, F, k, Du, Dv."""
+    bits, dt = _prec(precision)
+    u = np.array(u0, dtype=dt, copy=True, order="C")
+    v = np.array(v0, dtype=dt, copy=True, order="C")
+    p = np.array([float(params[k]) for k in GS_ORDER], dtype=dt)
+    R, C = u.shape
+    if _load().oracle_gs_run(R, C, _BC[bc], bits, _ptr(p), int(T), _ptr(u), _ptr(v)) != 0:
+        raise MemoryError("oracle_gs_run")
+    return u, v
+
+
+def cnn_input(img, B, z: float, bc: str, precision: str = "f32"):
+    """The Chua-Yang input layer w = (B * img) + z (cell_models.c); B is 3x3."""
+    bits, dt = _prec(precision)
+    g = np.array(img, dtype=dt, copy=True, order="C")
+    bz = np.array(list(np.asarray(B, dtype=np.float64).reshape(9)) + [float(z)], dtype=dt)
+    w = np.empty_like(g)
+    R, C = g.shape
+    _load().oracle_cnn_input(R, C, _BC[bc], bits, _ptr(bz), _ptr(g), _ptr(w))
+    return w
+
+
+def cnn_run(x0, w, dt_step: float, A, bc: str, T: int, precision: str = "f32"):
+    """T Chua-Yang steps of the state x with the fixed input layer w (cell_models.c)."""
+    bits, dt = _prec(precision)
+    x = np.array(x0, dtype=dt, copy=True, order="C")
+    ww = np.ascontiguousarray(w, dtype=dt)
+    p = np.array([float(dt_step)] + list(np.asarray(A, dtype=np.float64).reshape(9)), dtype=dt)
+    R, C = x.shape
+    if _load().oracle_cnn_run(R, C, _BC[bc], bits, _ptr(p), int(T), _ptr(x), _ptr(ww)) != 0:
+        raise MemoryError("oracle_cnn_run")
+    return x
