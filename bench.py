@@ -49,8 +49,8 @@ def parse():
                     help="first run a plain device copy of this size (scales HBM counters)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the differentiation and parameter-sweep workloads")
-    ap.add_argument("--only-extra", choices=["fwd_bwd", "batched", "small_batch", "atlas", "plain",
-                                                   "edge", "table1"],
+    ap.add_argument("--only-extra", choices=["fwd_bwd", "batched", "small_batch", "atlas", "models",
+                                                   "plain", "edge", "table1"],
                     help="run just this extra workload after the forward steps (profiling)")
     return ap.parse_args()
 
@@ -251,6 +251,41 @@ def bench_atlas(stream):
             "stats_ms": t_stats * 1e3, "stats_gbs": 12 * cells / t_stats / 1e9,
             "classes": {atlas.CLASSES[k]: int((cls == k).sum()) for k in range(4)},
             "paper_points": named}
+
+
+def bench_models(stream):
+    """The further cell models on the streamed kernel at the headline grid size:
+    Gray-Scott (dt=0.5, F=0.037, k=0.06, Du=0.2, Dv=0.1, periodic, u = 1 and
+    v = 0 with a seeded 512x512 square of (0.5, 0.25) plus U[0,0.05] noise) and
+    the Chua-Yang edge template (A = 2 at the centre, B = 8 / -1, z = -1,
+    dt = 0.1, zero-flux) on a 4096x4096 two-level rectangle image; T = 2000
+    each, default pass settings."""
+    import numpy as np
+    import torch
+    from paper_2102_10340_amd import Simulation
+    N, T = 4096, 2000
+    rng = np.random.default_rng(0)
+    u = np.ones((N, N), np.float32)
+    v = rng.uniform(0, 0.05, (N, N)).astype(np.float32)
+    u[1792:2304, 1792:2304] = 0.5
+    v[1792:2304, 1792:2304] += 0.25
+    out = {}
+    gs = Simulation.gray_scott(torch.from_numpy(u).cuda(), torch.from_numpy(v).cuda(), 0.5, 0.037,
+                               0.06, 0.2, 0.1, "periodic")
+    gs.step(16)
+    t = _timed(lambda: gs.step(T), stream)
+    gs.close()
+    out["gray_scott_gcells"] = N * N * T / t / 1e9
+    _, clean = W.rect_image(N, N, 1)
+    img = torch.from_numpy(np.where(clean > 0, 1.0, -1.0).astype(np.float32)).cuda()
+    cnn = Simulation.cnn(torch.zeros_like(img), img, [[0, 0, 0], [0, 2, 0], [0, 0, 0]],
+                         [[-1, -1, -1], [-1, 8, -1], [-1, -1, -1]], -1.0, 0.1, "zeroflux")
+    cnn.step(16)
+    t = _timed(lambda: cnn.step(T), stream)
+    cnn.close()
+    out["cnn_edge_gcells"] = N * N * T / t / 1e9
+    out["workload"] = "4096x4096, T=2000: Gray-Scott (periodic) and Chua-Yang edge CNN (zero-flux)"
+    return out
 
 
 def bench_plain(stream):
@@ -460,6 +495,8 @@ def main():
                 out["small_batch"] = bench_small_batch(stream)
             if args.only_extra in (None, "atlas"):
                 out["atlas"] = bench_atlas(stream)
+            if args.only_extra in (None, "models"):
+                out["models"] = bench_models(stream)
             if args.only_extra in (None, "plain"):
                 out["plain"] = bench_plain(stream)
             if args.only_extra in (None, "edge"):

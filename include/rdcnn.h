@@ -88,6 +88,45 @@ typedef struct rdcnn_sim *rdcnn_t;
 int rdcnn_create(rdcnn_t *out, int rows, int cols, int bc, const rdcnn_params_t *p,
                  const float *x_dev, float ka, float *buf0_dev, float *buf1_dev, void *stream);
 
+/* Built-in cell models for rdcnn_model_create. */
+enum {
+    RDCNN_MODEL_FITZHUGH_NAGUMO = 0,
+    RDCNN_MODEL_GRAY_SCOTT = 1,
+    RDCNN_MODEL_CNN = 2
+};
+
+/*
+ * rdcnn_model_create -- a grid of one of the built-in two-layer cell models,
+ * run by the same register-streamed kernel with the model's update swapped in.
+ * The paper closes (Sec. IV) by noting that its framework extends to any
+ * finite-difference time-domain or cellular model; this is that extension.
+ *   RDCNN_MODEL_FITZHUGH_NAGUMO  params (8): dt, a, b, eps, c, k3, Du, Dv
+ *       (Eq. (1)-(3)); state starts at (u0, v0).
+ *   RDCNN_MODEL_GRAY_SCOTT       params (5): dt, F, k, Du, Dv;
+ *       u+ = u + dt (Du Lap u - u v^2 + F (1 - u)),
+ *       v+ = v + dt (Dv Lap v + u v^2 - (F + k) v); state starts at (u0, v0).
+ *   RDCNN_MODEL_CNN              params (20): dt, A[9], B[9], z (3x3 templates
+ *       row-major NW, N, NE, W, C, E, SW, S, SE): a Chua-Yang cellular neural
+ *       network x+ = x + dt (-x + (A * y) + w), y = (|x+1| - |x-1|) / 2, with
+ *       w = (B * g) + z formed once from the input image g = v0 and kept as the
+ *       second layer; the state x starts at u0.
+ * Rounding orders are fixed per model (the CPU oracle's cell_models.c writes the
+ * same order), so results are bit-identical whatever the pass shape.  A CNN
+ * whose A template is not mirror symmetric runs one step per pass at a
+ * zero-flux edge (blocked passes would not reproduce the edge-copy rule).
+ * rdcnn_step, rdcnn_read, rdcnn_write_state, rdcnn_current, rdcnn_set_kernel
+ * (kind 0 or 2) and rdcnn_destroy apply as for rdcnn_create's grids; models
+ * other than FitzHugh-Nagumo use passes of 1, 2, 4 or 8 steps and 1 or 2
+ * columns per lane, and have no reverse pass (rdcnn_step_record,
+ * rdcnn_adjoint and rdcnn_set_params return RDCNN_EINVAL for them).
+ * u0_dev, v0_dev: device, rows*cols floats each; buf0/buf1 as for rdcnn_create.
+ * Errors: RDCNN_EINVAL (unknown model, wrong parameter count, non-finite
+ * parameter, bad size or buffer), RDCNN_EHIP, RDCNN_ENOMEM.
+ */
+int rdcnn_model_create(rdcnn_t *out, int model, int rows, int cols, int bc, const float *params,
+                       int nparams, const float *u0_dev, const float *v0_dev, float *buf0_dev,
+                       float *buf1_dev, void *stream);
+
 /*
  * rdcnn_step -- advance the grid by T time steps of Eq. (1)-(3) ("for t = 1..T").
  * T >= 0; T == 0 does nothing.  Asynchronous.  The current state alternates

@@ -44,6 +44,7 @@ _PAR = ctypes.POINTER(Params)
 
 _SIGS = {
     "rdcnn_create": [_PP, _I, _I, _I, _PAR, _P, _F, _P, _P, _P],
+    "rdcnn_model_create": [_PP, _I, _I, _I, _I, _P, _I, _P, _P, _P, _P, _P],
     "rdcnn_step": [_P, _LL],
     "rdcnn_read": [_P, _P, _P, _I],
     "rdcnn_write_state": [_P, _P, _P],

@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librdcnn.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["rd_api.hip", "rd_forward.hip", "rd_adjoint.hip", "rd_batch.hip", "rd_stats.hip"]
+SOURCES = ["rd_api.hip", "rd_forward.hip", "rd_adjoint.hip", "rd_batch.hip", "rd_stats.hip", "rd_models.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -26,6 +26,8 @@ struct rdcnn_sim {
     unsigned grad_mask;                    // gradients rdcnn_adjoint forms (bit q: param q)
     double *partial;                       // adjoint per-tile partial sums
     long long partial_cap;                 // tiles it can hold
+    int model;                             // rd::MODEL_*; g holds the FHN gene
+    float mparams[rd::kModelParams];       // parameters of the other models
 };
 
 namespace {
@@ -87,10 +89,45 @@ void auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows, bool r
     }
 }
 
+// Steps of a model other than FitzHugh-Nagumo: passes of 8, 4, 2 or 1 steps
+// (the instantiated depths), one step per pass at a zero-flux edge when the
+// update is not mirror-exact for these parameters.
+int run_model_steps(rdcnn_sim *h, long long n)
+{
+    if (h->kind == 1) return fail(RDCNN_EINVAL, "rdcnn_step: the one-thread-per-cell kernel "
+                                                "exists for FitzHugh-Nagumo only");
+    int cpl = h->cpl, depth = h->depth, seg = h->seg_rows;
+    if (h->kind == 0) {
+        cpl = h->R >= 2048 && h->C >= 2048 ? 2 : 1;
+        depth = 8;
+        seg = 0;
+    }
+    if (cpl > 2) cpl = 2;
+    if (h->bc == RDCNN_BC_ZEROFLUX && !rd::model_mirror_exact(h->model, h->mparams)) depth = 1;
+    while (n > 0) {
+        int k = 8;
+        while (k > 1 && (k > depth || k > n)) k >>= 1;
+        rd::StreamGeom geom;
+        if (!rd::stream_geometry(h->R, h->C, cpl, k, seg, &geom))
+            return fail(RDCNN_EINVAL, "rdcnn_step: cannot tile %dx%d with cpl=%d depth=%d", h->R,
+                        h->C, cpl, k);
+        hipError_t e = rd::launch_model(h->model, h->buf[h->cur], h->buf[1 - h->cur], h->R, h->C,
+                                        h->bc, h->mparams, geom, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "rdcnn_step: model kernel launch");
+        h->cur = 1 - h->cur;
+        n -= k;
+    }
+    return RDCNN_OK;
+}
+
 // Run n steps from buf[cur]; flips cur once per pass.  If rec is not null the
 // state each step starts from is also written to rec[0..n-1] (2*R*C floats each).
 int run_steps(rdcnn_sim *h, long long n, float *rec)
 {
+    if (h->model != rd::MODEL_FHN) {
+        if (rec) return fail(RDCNN_EINVAL, "rdcnn_step_record: FitzHugh-Nagumo grids only");
+        return run_model_steps(h, n);
+    }
     long long q = 0;
     int kind = h->kind, cpl = h->cpl, depth = h->depth, seg = h->seg_rows;
     if (kind == 0) {
@@ -143,36 +180,29 @@ void adj_auto_config(const rdcnn_sim *, int *cpl, int *depth, int *seg_rows)
     *seg_rows = 0;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char *rdcnn_last_error(void) { return g_err; }
-
-int rdcnn_create(rdcnn_t *out, int rows, int cols, int bc, const rdcnn_params_t *p,
-                 const float *x_dev, float ka, float *buf0_dev, float *buf1_dev, void *stream)
+int check_grid(const char *who, int rows, int cols, int bc, const float *buf0, const float *buf1)
 {
-    if (!out) return fail(RDCNN_EINVAL, "rdcnn_create: out is NULL");
-    *out = nullptr;
-    if (rows < 1 || cols < 1) return fail(RDCNN_EINVAL, "rdcnn_create: grid %dx%d", rows, cols);
+    if (rows < 1 || cols < 1) return fail(RDCNN_EINVAL, "%s: grid %dx%d", who, rows, cols);
     if ((long long)rows * cols >= (1LL << 30))
-        return fail(RDCNN_EINVAL, "rdcnn_create: grid of %lld cells; at most 2^30-1 (one plane "
-                    "must stay below 4 GiB)", (long long)rows * cols);
+        return fail(RDCNN_EINVAL, "%s: grid of %lld cells; at most 2^30-1 (one plane must stay "
+                    "below 4 GiB)", who, (long long)rows * cols);
     if (bc != RDCNN_BC_PERIODIC && bc != RDCNN_BC_ZEROFLUX)
-        return fail(RDCNN_EINVAL, "rdcnn_create: unknown boundary rule %d", bc);
-    if (!p || !finite_params(p)) return fail(RDCNN_EINVAL, "rdcnn_create: missing or non-finite parameters");
-    if (!isfinite(ka)) return fail(RDCNN_EINVAL, "rdcnn_create: non-finite ka");
-    if (!x_dev || !buf0_dev || !buf1_dev)
-        return fail(RDCNN_EINVAL, "rdcnn_create: NULL device buffer");
-    if (buf0_dev == buf1_dev) return fail(RDCNN_EINVAL, "rdcnn_create: the two state buffers alias");
+        return fail(RDCNN_EINVAL, "%s: unknown boundary rule %d", who, bc);
+    if (!buf0 || !buf1) return fail(RDCNN_EINVAL, "%s: NULL device buffer", who);
+    if (buf0 == buf1) return fail(RDCNN_EINVAL, "%s: the two state buffers alias", who);
+    return RDCNN_OK;
+}
+
+rdcnn_sim *new_sim(int rows, int cols, int bc, float *buf0, float *buf1, void *stream)
+{
     rdcnn_sim *h = new (std::nothrow) rdcnn_sim;
-    if (!h) return fail(RDCNN_ENOMEM, "rdcnn_create: out of host memory");
+    if (!h) return nullptr;
     h->R = rows;
     h->C = cols;
     h->bc = bc;
-    h->g = to_gene(p);
-    h->buf[0] = buf0_dev;
-    h->buf[1] = buf1_dev;
+    h->g = rd::Gene{};
+    h->buf[0] = buf0;
+    h->buf[1] = buf1;
     h->cur = 0;
     h->stream = (hipStream_t)stream;
     h->kind = 0;
@@ -185,10 +215,78 @@ int rdcnn_create(rdcnn_t *out, int rows, int cols, int bc, const rdcnn_params_t 
     h->grad_mask = 0xFFu;
     h->partial = nullptr;
     h->partial_cap = 0;
+    h->model = rd::MODEL_FHN;
+    for (float &x : h->mparams) x = 0.0f;
+    return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rdcnn_last_error(void) { return g_err; }
+
+int rdcnn_create(rdcnn_t *out, int rows, int cols, int bc, const rdcnn_params_t *p,
+                 const float *x_dev, float ka, float *buf0_dev, float *buf1_dev, void *stream)
+{
+    if (!out) return fail(RDCNN_EINVAL, "rdcnn_create: out is NULL");
+    *out = nullptr;
+    const int rc = check_grid("rdcnn_create", rows, cols, bc, buf0_dev, buf1_dev);
+    if (rc != RDCNN_OK) return rc;
+    if (!p || !finite_params(p)) return fail(RDCNN_EINVAL, "rdcnn_create: missing or non-finite parameters");
+    if (!isfinite(ka)) return fail(RDCNN_EINVAL, "rdcnn_create: non-finite ka");
+    if (!x_dev) return fail(RDCNN_EINVAL, "rdcnn_create: NULL device buffer");
+    rdcnn_sim *h = new_sim(rows, cols, bc, buf0_dev, buf1_dev, stream);
+    if (!h) return fail(RDCNN_ENOMEM, "rdcnn_create: out of host memory");
+    h->g = to_gene(p);
     hipError_t e = rd::launch_init(x_dev, ka, buf0_dev, (long long)rows * cols, h->stream);
     if (e != hipSuccess) {
         delete h;
         return hip_fail(e, "rdcnn_create: init launch");
+    }
+    *out = h;
+    return RDCNN_OK;
+}
+
+int rdcnn_model_create(rdcnn_t *out, int model, int rows, int cols, int bc, const float *params,
+                       int nparams, const float *u0_dev, const float *v0_dev, float *buf0_dev,
+                       float *buf1_dev, void *stream)
+{
+    if (!out) return fail(RDCNN_EINVAL, "rdcnn_model_create: out is NULL");
+    *out = nullptr;
+    const int rc = check_grid("rdcnn_model_create", rows, cols, bc, buf0_dev, buf1_dev);
+    if (rc != RDCNN_OK) return rc;
+    const int want = rd::model_nparams(model);
+    if (want < 0) return fail(RDCNN_EINVAL, "rdcnn_model_create: unknown model %d", model);
+    if (nparams != want || !params)
+        return fail(RDCNN_EINVAL, "rdcnn_model_create: model %d takes %d parameters, got %d",
+                    model, want, nparams);
+    for (int i = 0; i < nparams; ++i)
+        if (!isfinite(params[i]))
+            return fail(RDCNN_EINVAL, "rdcnn_model_create: parameter %d is not finite", i);
+    if (!u0_dev || !v0_dev) return fail(RDCNN_EINVAL, "rdcnn_model_create: NULL initial state");
+    rdcnn_sim *h = new_sim(rows, cols, bc, buf0_dev, buf1_dev, stream);
+    if (!h) return fail(RDCNN_ENOMEM, "rdcnn_model_create: out of host memory");
+    h->model = model;
+    for (int i = 0; i < nparams; ++i) h->mparams[i] = params[i];
+    if (model == rd::MODEL_FHN) {
+        const rdcnn_params_t p{params[0], params[1], params[2], params[3],
+                               params[4], params[5], params[6], params[7]};
+        h->g = to_gene(&p);
+    }
+    const size_t n = (size_t)rows * cols;
+    hipError_t e = hipMemcpyAsync(buf0_dev, u0_dev, sizeof(float) * n, hipMemcpyDeviceToDevice,
+                                  h->stream);
+    if (e == hipSuccess) {
+        if (model == rd::MODEL_CNN)  // second layer: w = (B * image) + z
+            e = rd::launch_cnn_input(v0_dev, params + 10, rows, cols, bc, buf0_dev + n, h->stream);
+        else
+            e = hipMemcpyAsync(buf0_dev + n, v0_dev, sizeof(float) * n, hipMemcpyDeviceToDevice,
+                               h->stream);
+    }
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "rdcnn_model_create: initial state");
     }
     *out = h;
     return RDCNN_OK;
@@ -232,6 +330,8 @@ int rdcnn_adjoint(rdcnn_t h, const float *states_dev, long long S, float *adj_de
                   float *adj_tmp_dev, double *dtheta_dev)
 {
     if (!h) return fail(RDCNN_EINVAL, "rdcnn_adjoint: NULL handle");
+    if (h->model != rd::MODEL_FHN)
+        return fail(RDCNN_EINVAL, "rdcnn_adjoint: FitzHugh-Nagumo grids only");
     if (S < 0) return fail(RDCNN_EINVAL, "rdcnn_adjoint: S = %lld < 0", S);
     if (!adj_dev || !adj_tmp_dev || !dtheta_dev || (S > 0 && !states_dev))
         return fail(RDCNN_EINVAL, "rdcnn_adjoint: NULL argument");
@@ -339,6 +439,8 @@ int rdcnn_set_params(rdcnn_t h, const rdcnn_params_t *p)
 {
     if (!h || !p) return fail(RDCNN_EINVAL, "rdcnn_set_params: NULL argument");
     if (!finite_params(p)) return fail(RDCNN_EINVAL, "rdcnn_set_params: non-finite parameter");
+    if (h->model != rd::MODEL_FHN)
+        return fail(RDCNN_EINVAL, "rdcnn_set_params: FitzHugh-Nagumo grids only");
     h->g = to_gene(p);
     return RDCNN_OK;
 }

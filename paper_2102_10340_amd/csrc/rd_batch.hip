@@ -61,11 +61,11 @@ __global__ __launch_bounds__(64) void batch_step_kernel(BatchArgs B)
     t.setup(A.t, id, bt.x0, bt.y0, bt.y1);
     if (t.fast) {
         if (t.y0 >= K && t.y1 + K <= in.R)
-            stream_body<CPL, K, false, true, true>(A, t);
+            stream_body<ModelFHN, CPL, K, false, true, true>(A, t);
         else
-            stream_body<CPL, K, false, true, false>(A, t);
+            stream_body<ModelFHN, CPL, K, false, true, false>(A, t);
     } else {
-        stream_body<CPL, K, false, false, false>(A, t);
+        stream_body<ModelFHN, CPL, K, false, false, false>(A, t);
     }
 }
 

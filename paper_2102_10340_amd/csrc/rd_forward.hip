@@ -91,11 +91,11 @@ __global__ __launch_bounds__(64) void stream_step_kernel(StreamArgs A)
     if (!t.init(A.t)) return;
     if (t.fast) {
         if (t.y0 >= K && t.y1 + K <= A.t.R)
-            stream_body<CPL, K, REC, true, true>(A, t);
+            stream_body<ModelFHN, CPL, K, REC, true, true>(A, t);
         else
-            stream_body<CPL, K, REC, true, false>(A, t);
+            stream_body<ModelFHN, CPL, K, REC, true, false>(A, t);
     } else {
-        stream_body<CPL, K, REC, false, false>(A, t);
+        stream_body<ModelFHN, CPL, K, REC, false, false>(A, t);
     }
 }
 

@@ -6,24 +6,32 @@
 // rows; it walks down the rows once, keeping three rows of (u, v) per time level
 // in registers (see the slot scheme below).  East/west neighbours across lanes
 // come from DPP wave shifts, north/south ones from the register window.
+//
+// The body is generic over the cell model M (rd_models.h): the FitzHugh-Nagumo
+// kernels are its ModelFHN instance, and further models reuse the same
+// streaming, tiling and boundary handling.  Models that read the diagonal
+// neighbours get them from DPP shifts of the north and south rows.
 #pragma once
 
+#include "rd_models.h"
 #include "rd_stream.h"
 
 namespace rd {
 
-struct StreamArgs {
+template <class M>
+struct StreamArgsT {
     TileArgs t;
     const float *in;
     float *out;
-    Gene g;
+    typename M::Params g;
     float *rec;  // recording: level j of the pass goes to state j of rec (null: off)
 };
+using StreamArgs = StreamArgsT<ModelFHN>;
 
 // ROWS_IN: every row the tile reads lies inside the grid, so row offsets need
 // no boundary mapping (true for all but the first and last segment of a strip).
-template <int CPL, int K, bool REC, bool FAST, bool ROWS_IN>
-__device__ __forceinline__ void stream_body(const StreamArgs &A, const Tile<CPL> &t)
+template <class M, int CPL, int K, bool REC, bool FAST, bool ROWS_IN>
+__device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<CPL> &t)
 {
     const int C = A.t.C, R = A.t.R, bc = A.t.bc;
     const unsigned pbytes = 4u * (unsigned)R * (unsigned)C;  // one plane
@@ -32,7 +40,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs &A, const Tile<CPL>
     const Buf ou(A.out, pbytes), ov(A.out + (size_t)R * C, pbytes);
     // K recorded states, u plane then v plane each: state j at byte 2*j*pbytes.
     const Buf rb(REC ? A.rec : A.in, REC ? 2u * (unsigned)K * pbytes : 0u);
-    const Gene g = A.g;
+    const typename M::Params g = A.g;
     const int y0 = t.y0, y1 = t.y1;
 
     const int rbase = y0 - K;                 // first row read (level 0)
@@ -71,27 +79,48 @@ __device__ __forceinline__ void stream_body(const StreamArgs &A, const Tile<CPL>
             // Level j+1 has all three input rows from it = 2j+2 on; rows made
             // after it = n_real are beyond the segment's cone.
             if (it >= 2 * j + 2 && it < n_real) {
+                // lane-shifted edge columns of the centre row (and, for models
+                // reading diagonals, of the north and south rows)
                 const float lu = from_left_lane(bu[j][sl.cs][CPL - 1]);
                 const float ru = from_right_lane(bu[j][sl.cs][0]);
                 const float lv = from_left_lane(bv[j][sl.cs][CPL - 1]);
                 const float rv = from_right_lane(bv[j][sl.cs][0]);
+                float luN = 0.0f, ruN = 0.0f, lvN = 0.0f, rvN = 0.0f;
+                float luS = 0.0f, ruS = 0.0f, lvS = 0.0f, rvS = 0.0f;
+                if (M::kDiag) {
+                    luN = from_left_lane(bu[j][sl.ps][CPL - 1]);
+                    ruN = from_right_lane(bu[j][sl.ps][0]);
+                    lvN = from_left_lane(bv[j][sl.ps][CPL - 1]);
+                    rvN = from_right_lane(bv[j][sl.ps][0]);
+                    luS = from_left_lane(bu[j][sl.ns][CPL - 1]);
+                    ruS = from_right_lane(bu[j][sl.ns][0]);
+                    lvS = from_left_lane(bv[j][sl.ns][CPL - 1]);
+                    rvS = from_right_lane(bv[j][sl.ns][0]);
+                }
 #pragma unroll
                 for (int e = 0; e < CPL; ++e) {
-                    const float uW = e == 0 ? lu : bu[j][sl.cs][e - 1];
-                    const float uE = e == CPL - 1 ? ru : bu[j][sl.cs][e + 1];
-                    const float vW = e == 0 ? lv : bv[j][sl.cs][e - 1];
-                    const float vE = e == CPL - 1 ? rv : bv[j][sl.cs][e + 1];
-                    // The lane-shifted neighbour goes first in its add so the
-                    // compiler can fold the shift into it (a + b == b + a
-                    // exactly, so the result does not change).
-                    if (CPL > 1 && e == CPL - 1)
-                        cell_update(g, bu[j][sl.cs][e], bv[j][sl.cs][e], bu[j][sl.ps][e],
-                                    bu[j][sl.ns][e], uE, uW, bv[j][sl.ps][e], bv[j][sl.ns][e], vE,
-                                    vW, du[e], dv[e]);
-                    else
-                        cell_update(g, bu[j][sl.cs][e], bv[j][sl.cs][e], bu[j][sl.ps][e],
-                                    bu[j][sl.ns][e], uW, uE, bv[j][sl.ps][e], bv[j][sl.ns][e], vW,
-                                    vE, du[e], dv[e]);
+                    Nbhd n;
+                    n.u = bu[j][sl.cs][e];
+                    n.v = bv[j][sl.cs][e];
+                    n.uN = bu[j][sl.ps][e];
+                    n.uS = bu[j][sl.ns][e];
+                    n.vN = bv[j][sl.ps][e];
+                    n.vS = bv[j][sl.ns][e];
+                    n.uW = e == 0 ? lu : bu[j][sl.cs][e - 1];
+                    n.uE = e == CPL - 1 ? ru : bu[j][sl.cs][e + 1];
+                    n.vW = e == 0 ? lv : bv[j][sl.cs][e - 1];
+                    n.vE = e == CPL - 1 ? rv : bv[j][sl.cs][e + 1];
+                    if (M::kDiag) {
+                        n.uNW = e == 0 ? luN : bu[j][sl.ps][e - 1];
+                        n.uNE = e == CPL - 1 ? ruN : bu[j][sl.ps][e + 1];
+                        n.vNW = e == 0 ? lvN : bv[j][sl.ps][e - 1];
+                        n.vNE = e == CPL - 1 ? rvN : bv[j][sl.ps][e + 1];
+                        n.uSW = e == 0 ? luS : bu[j][sl.ns][e - 1];
+                        n.uSE = e == CPL - 1 ? ruS : bu[j][sl.ns][e + 1];
+                        n.vSW = e == 0 ? lvS : bv[j][sl.ns][e - 1];
+                        n.vSE = e == CPL - 1 ? rvS : bv[j][sl.ns][e + 1];
+                    }
+                    M::update(g, n, du[e], dv[e]);
                 }
             }
             // The next level-0 row is loaded before this iteration's stores:

@@ -64,6 +64,22 @@ hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, cons
                          const StreamGeom &geom, hipStream_t s, float *rec = nullptr,
                          long long rec_q0 = 0);
 
+// Cell models other than FitzHugh-Nagumo on the same streamed kernel
+// (rd_models.h).  Their passes take depth 1, 2, 4 or 8 and cols_per_lane 1 or 2.
+enum { MODEL_FHN = 0, MODEL_GRAY_SCOTT = 1, MODEL_CNN = 2 };
+constexpr int kModelParams = 20;  // largest parameter vector (CNN: dt, A[9], B[9], z)
+inline int model_nparams(int model)
+{
+    return model == MODEL_FHN ? 8 : model == MODEL_GRAY_SCOTT ? 5 : model == MODEL_CNN ? 20 : -1;
+}
+// Whether blocked passes are exact at a zero-flux edge for these parameters.
+bool model_mirror_exact(int model, const float *params);
+hipError_t launch_model(int model, const float *in, float *out, int R, int C, int bc,
+                        const float *params, const StreamGeom &geom, hipStream_t s);
+// CNN input layer: w = (B * img) + z (bz = B[9], z), with the grid's boundary rule.
+hipError_t launch_cnn_input(const float *img, const float *bz, int R, int C, int bc, float *w,
+                            hipStream_t s);
+
 // `geom.depth` reverse steps: (lam, mu) `in` -> `out`, reading states
 // states[q_top], states[q_top-1], ...; adds each tile's eight sums to partial.
 // lam_sums: also form the sums only dJ/ddt, dJ/dc and dJ/dk3 need.

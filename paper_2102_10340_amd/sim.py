@@ -42,6 +42,43 @@ class Simulation:
                                    self.buf[0].data_ptr(), self.buf[1].data_ptr(),
                                    _stream_handle(self.device)))
 
+    MODELS = {"fitzhugh_nagumo": 0, "gray_scott": 1, "cnn": 2}
+
+    @classmethod
+    def model(cls, name: str, u0: torch.Tensor, v0: torch.Tensor, params, bc: str = "zeroflux"):
+        """A grid of a built-in cell model (rdcnn_model_create): name is one of
+        MODELS, params the model's float vector, (u0, v0) its two starting
+        layers (for "cnn": the state x0 and the input image)."""
+        if u0.dim() != 2 or u0.shape != v0.shape or u0.dtype != torch.float32 or not u0.is_cuda:
+            raise ValueError("u0, v0 must be 2-D float32 CUDA tensors of one shape")
+        sim = cls.__new__(cls)
+        sim.device = u0.device
+        sim.rows, sim.cols = int(u0.shape[0]), int(u0.shape[1])
+        sim.bc = bc
+        sim._x = (u0.contiguous(), v0.contiguous())
+        sim.buf = [torch.empty((2, sim.rows, sim.cols), dtype=torch.float32, device=sim.device)
+                   for _ in range(2)]
+        sim._h = ctypes.c_void_p()
+        p = (ctypes.c_float * len(params))(*[float(x) for x in params])
+        with torch.cuda.device(sim.device):
+            check(lib.rdcnn_model_create(ctypes.byref(sim._h), cls.MODELS[name], sim.rows, sim.cols,
+                                         BC[bc], p, len(params), sim._x[0].data_ptr(),
+                                         sim._x[1].data_ptr(), sim.buf[0].data_ptr(),
+                                         sim.buf[1].data_ptr(), _stream_handle(sim.device)))
+        return sim
+
+    @classmethod
+    def gray_scott(cls, u0, v0, dt, F, k, Du, Dv, bc: str = "periodic"):
+        """Gray-Scott reaction-diffusion on the streamed kernel."""
+        return cls.model("gray_scott", u0, v0, [dt, F, k, Du, Dv], bc)
+
+    @classmethod
+    def cnn(cls, x0, image, A, B, z, dt, bc: str = "zeroflux"):
+        """Chua-Yang cellular neural network with 3x3 templates A, B and bias z."""
+        a = [float(v) for v in torch.as_tensor(A, dtype=torch.float64).reshape(9)]
+        b = [float(v) for v in torch.as_tensor(B, dtype=torch.float64).reshape(9)]
+        return cls.model("cnn", x0, image, [dt] + a + b + [float(z)], bc)
+
     @classmethod
     def from_state(cls, u0: torch.Tensor, v0: torch.Tensor, gene, bc: str = "zeroflux"):
         """A grid whose state starts at (u0, v0) instead of k_a x."""

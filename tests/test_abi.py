@@ -69,6 +69,25 @@ def test_create_rejects_bad_arguments(L):
                               None) == L.EINVAL
 
 
+def test_model_create_rejects_bad_arguments(L):
+    h = ctypes.c_void_p()
+    gs = (ctypes.c_float * 5)(0.5, 0.037, 0.06, 0.2, 0.1)
+    bad = (ctypes.c_float * 5)(0.5, float("nan"), 0.06, 0.2, 0.1)
+    args = (0x2000, 0x3000, 0x4000, 0x5000, None)
+    assert L.lib.rdcnn_model_create(ctypes.byref(h), 7, 8, 8, 0, gs, 5, *args) == L.EINVAL
+    assert L.lib.rdcnn_model_create(ctypes.byref(h), 1, 8, 8, 0, gs, 4, *args) == L.EINVAL
+    assert L.lib.rdcnn_model_create(ctypes.byref(h), 2, 8, 8, 0, gs, 5, *args) == L.EINVAL
+    assert L.lib.rdcnn_model_create(ctypes.byref(h), 1, 8, 8, 0, bad, 5, *args) == L.EINVAL
+    assert L.lib.rdcnn_model_create(ctypes.byref(h), 1, 0, 8, 0, gs, 5, *args) == L.EINVAL
+    assert L.lib.rdcnn_model_create(ctypes.byref(h), 1, 8, 8, 5, gs, 5, *args) == L.EINVAL
+    assert L.lib.rdcnn_model_create(ctypes.byref(h), 1, 8, 8, 0, gs, 5, None, 0x3000, 0x4000,
+                                    0x5000, None) == L.EINVAL
+    assert L.lib.rdcnn_model_create(ctypes.byref(h), 1, 8, 8, 0, gs, 5, 0x2000, 0x3000, 0x4000,
+                                    0x4000, None) == L.EINVAL
+    assert L.lib.rdcnn_model_create(None, 1, 8, 8, 0, gs, 5, *args) == L.EINVAL
+    assert not h.value
+
+
 def test_null_handle_calls_fail_cleanly(L):
     assert L.lib.rdcnn_step(None, 5) == L.EINVAL
     assert L.lib.rdcnn_read(None, None, None, 1) == L.EINVAL
