@@ -320,6 +320,7 @@ def bench_edge_fit(stream, n_img=64, iters=4):
     p = torch.tensor([g["Du"], g["Dv"], -g["eps"]], dtype=torch.float64, requires_grad=True)
     opt = torch.optim.Adam([p], lr=0.02)
     losses, times = [], []
+    streams = [torch.cuda.Stream() for _ in range(4)]
     for _ in range(iters):
         opt.zero_grad()
         theta = torch.stack([torch.tensor(g["dt"], dtype=torch.float64),
@@ -329,13 +330,21 @@ def bench_edge_fit(stream, n_img=64, iters=4):
                              torch.tensor(g["k3"], dtype=torch.float64), p[0], p[1]])
 
         def step():
-            total = 0.0
-            for x, tg in zip(imgs, targets):
-                u, _ = simulate(x, theta, T, "zeroflux", grads=("Du", "Dv", "eps"))
-                loss = ((u - tg) ** 2).mean() / n_img
-                loss.backward(retain_graph=True)
-                total += float(loss)
-            return total
+            # Images go round-robin to a few streams so that their small
+            # launches overlap (autograd runs each backward on its forward's
+            # stream); one backward over the summed loss, one host sync.
+            losses = []
+            for i, (x, tg) in enumerate(zip(imgs, targets)):
+                s = streams[i % len(streams)]
+                s.wait_stream(stream)
+                with torch.cuda.stream(s):
+                    u, _ = simulate(x, theta, T, "zeroflux", grads=("Du", "Dv", "eps"))
+                    losses.append(((u - tg) ** 2).mean() / n_img)
+            for s in streams:
+                stream.wait_stream(s)
+            total = torch.stack(losses).sum()
+            total.backward()
+            return float(total)
 
         t0 = time.perf_counter()
         losses.append(step())
