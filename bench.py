@@ -306,10 +306,13 @@ def bench_edge_fit(stream, n_img=64, iters=4):
     """Edge detection fitted by gradient: 64 synthetic 1024x1024 images (20..60
     random rectangles of levels U[-1,1] plus N(0, 0.05^2) noise), x = image,
     T = 50, zero-flux; Du, Dv and epsilon (shared by all images) fitted by Adam
-    to the normalized Sobel magnitude of the clean images.  Reports the loss
-    curve and the fwd+bwd rate over all images."""
+    to the normalized Sobel magnitude of the clean images.  Each iteration is
+    one batched forward+backward over all 64 images (simulate_batch: recording
+    batch kernel, batched adjoint kernel).  Reports the loss curve, the fwd+bwd
+    rate, and for comparison one iteration run image by image over four
+    streams with the single-grid path."""
     import torch
-    from paper_2102_10340_amd import simulate
+    from paper_2102_10340_amd import simulate, simulate_batch
     N, T = 1024, 50
     imgs, targets = [], []
     for i in range(n_img):
@@ -319,35 +322,43 @@ def bench_edge_fit(stream, n_img=64, iters=4):
     g = W.PLAIN_GENE
     p = torch.tensor([g["Du"], g["Dv"], -g["eps"]], dtype=torch.float64, requires_grad=True)
     opt = torch.optim.Adam([p], lr=0.02)
-    losses, times = [], []
+    grads = ("Du", "Dv", "eps")
+
+    def theta_of(q):
+        return torch.stack([torch.tensor(g["dt"], dtype=torch.float64),
+                            torch.tensor(g["a"], dtype=torch.float64),
+                            torch.tensor(g["b"], dtype=torch.float64), -q[2],
+                            torch.tensor(g["c"], dtype=torch.float64),
+                            torch.tensor(g["k3"], dtype=torch.float64), q[0], q[1]])
+
+    def batched(theta):
+        outs = simulate_batch(imgs, theta, T, "zeroflux", grads=grads)
+        total = torch.stack([((u - tg) ** 2).mean() for (u, _), tg in zip(outs, targets)]).sum()
+        total = total / n_img
+        total.backward()
+        return float(total.detach())
+
     streams = [torch.cuda.Stream() for _ in range(4)]
+
+    def per_image(theta):
+        losses = []
+        for i, (x, tg) in enumerate(zip(imgs, targets)):
+            s = streams[i % len(streams)]
+            s.wait_stream(stream)
+            with torch.cuda.stream(s):
+                u, _ = simulate(x, theta, T, "zeroflux", grads=grads)
+                losses.append(((u - tg) ** 2).mean() / n_img)
+        for s in streams:
+            stream.wait_stream(s)
+        total = torch.stack(losses).sum()
+        total.backward()
+        return float(total)
+
+    losses, times = [], []
     for _ in range(iters):
         opt.zero_grad()
-        theta = torch.stack([torch.tensor(g["dt"], dtype=torch.float64),
-                             torch.tensor(g["a"], dtype=torch.float64),
-                             torch.tensor(g["b"], dtype=torch.float64), -p[2],
-                             torch.tensor(g["c"], dtype=torch.float64),
-                             torch.tensor(g["k3"], dtype=torch.float64), p[0], p[1]])
-
-        def step():
-            # Images go round-robin to a few streams so that their small
-            # launches overlap (autograd runs each backward on its forward's
-            # stream); one backward over the summed loss, one host sync.
-            losses = []
-            for i, (x, tg) in enumerate(zip(imgs, targets)):
-                s = streams[i % len(streams)]
-                s.wait_stream(stream)
-                with torch.cuda.stream(s):
-                    u, _ = simulate(x, theta, T, "zeroflux", grads=("Du", "Dv", "eps"))
-                    losses.append(((u - tg) ** 2).mean() / n_img)
-            for s in streams:
-                stream.wait_stream(s)
-            total = torch.stack(losses).sum()
-            total.backward()
-            return float(total)
-
         t0 = time.perf_counter()
-        losses.append(step())
+        losses.append(batched(theta_of(p)))
         stream.synchronize()
         times.append(time.perf_counter() - t0)
         opt.step()
@@ -356,10 +367,20 @@ def bench_edge_fit(stream, n_img=64, iters=4):
             p[1].clamp_(0.0, 2.4)
             p[2].clamp_(1e-3, 1.0)
     t = min(times)
+    q = p.detach().clone().requires_grad_(True)
+    per_image(theta_of(q))  # warm
+    q.grad = None
+    stream.synchronize()
+    t0 = time.perf_counter()
+    per_image(theta_of(q))
+    stream.synchronize()
+    t_img = time.perf_counter() - t0
     return {"workload": f"{n_img} images 1024x1024, T=50, fit Du, Dv, eps by Adam to Sobel targets",
             "loss_curve": losses, "params_final": {"Du": float(p[0]), "Dv": float(p[1]),
                                                    "epsilon": float(p[2])},
-            "fwd_bwd_gcells": n_img * N * N * T / t / 1e9, "iter_s": t}
+            "fwd_bwd_gcells": n_img * N * N * T / t / 1e9, "iter_s": t,
+            "per_image_streams_gcells": n_img * N * N * T / t_img / 1e9,
+            "batched_vs_per_image": t_img / t}
 
 
 # Table I of the paper: PyCUDA on a Tesla P100-PCIE, 10^4 iterations of the

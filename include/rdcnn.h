@@ -285,6 +285,52 @@ int rdcnn_batch_use_lds(rdcnn_batch_t b, int on);
 int rdcnn_batch_lds_instances(rdcnn_batch_t b, int *count);
 
 /*
+ * rdcnn_batch_write_state -- replace the current packed state with `packed`
+ * (device, buf_floats floats in this batch's layout).  Stream-ordered.
+ * Errors: RDCNN_EINVAL (NULL), RDCNN_EHIP.
+ */
+int rdcnn_batch_write_state(rdcnn_batch_t b, const float *packed);
+
+/*
+ * rdcnn_batch_step_record -- rdcnn_batch_step for T steps, also writing the
+ * state every step starts from: packed state q (the whole batch before step q,
+ * q = 0 .. T-1) goes to traj + q * buf_floats.  traj: device, T * buf_floats
+ * floats, caller-owned.  Recording runs every instance on the streamed kernel
+ * (no in-LDS path, no graph) with 1 or 2 columns per lane and at most 8 steps
+ * per pass, fewer where one instance's span of a pass's states would pass
+ * 4 GiB.  Results equal rdcnn_batch_step's bit for bit.  This is the forward
+ * half of the batched reverse pass (below).  Errors: RDCNN_EINVAL, RDCNN_ENOMEM,
+ * RDCNN_EHIP.
+ */
+int rdcnn_batch_step_record(rdcnn_batch_t b, long long T, float *traj);
+
+/*
+ * rdcnn_batch_set_adjoint_kernel -- pass shape of rdcnn_batch_adjoint: depth
+ * (reverse steps per pass: 1, 2, 4 or 8), cols_per_lane (1 or 2), seg_rows
+ * (rows per tile); 0 keeps the default (4, 2, 64).  Errors: RDCNN_EINVAL.
+ */
+int rdcnn_batch_set_adjoint_kernel(rdcnn_batch_t b, int depth, int cols_per_lane, int seg_rows);
+
+/*
+ * rdcnn_batch_adjoint -- the reverse pass of rdcnn_adjoint for every instance
+ * of the batch at once (the transpose of the step's Jacobian, Eq. (1)-(3)):
+ * traj holds S packed states, state q at traj + q * buf_floats, the states the
+ * last S steps started from (as rdcnn_batch_step_record writes them).  adj
+ * (device, packed layout, caller-owned): on entry dJ/ds after the S steps, on
+ * return dJ/ds before them, per instance (u plane then v plane).  adj_tmp:
+ * scratch of buf_floats floats.  dtheta (device, n x 8 doubles,
+ * instance-major, order dt, a, b, eps, c, k3, Du, Dv): each instance's
+ * parameter gradients are added to its row; gradients whose bit is clear in
+ * mask are not formed and come back NaN.  Sums are folded per instance in a
+ * fixed order (deterministic).  The first call allocates the tile list and the
+ * per-tile partial buffer (kept until destroy).  Errors: RDCNN_EINVAL (NULL or
+ * aliased buffers, S < 0, packed state too large for the depth), RDCNN_ENOMEM,
+ * RDCNN_EHIP.
+ */
+int rdcnn_batch_adjoint(rdcnn_batch_t b, const float *traj, long long S, float *adj,
+                        float *adj_tmp, unsigned mask, double *dtheta);
+
+/*
  * rdcnn_batch_stats -- per-instance statistics of the current state for a
  * parameter atlas (the automated form of the (Du, Dv) scans of Sec. III.A,
  * Fig. 9).  For instance i with N cells, out[8*i + k] (doubles, device) is

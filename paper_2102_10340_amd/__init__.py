@@ -13,7 +13,8 @@ _EXPORTS = {
     "LIB_PATH": "._lib", "Simulation": ".sim", "init_backward": ".sim",
     "RDCNNFunction": ".autograd", "RDCNNStateFunction": ".autograd", "simulate": ".autograd",
     "simulate_state": ".autograd", "default_segment": ".autograd", "Batch": ".batch",
-    "tune": ".tune",
+    "RDCNNBatchFunction": ".autograd", "simulate_batch": ".autograd", "tune": ".tune",
+    "atlas": ".atlas",
 }
 
 __all__ = sorted(_EXPORTS)

@@ -65,6 +65,10 @@ _SIGS = {
     "rdcnn_batch_use_lds": [_P, _I],
     "rdcnn_batch_lds_instances": [_P, ctypes.POINTER(ctypes.c_int)],
     "rdcnn_batch_stats": [_P, _P, _P, _F, _F, _P],
+    "rdcnn_batch_write_state": [_P, _P],
+    "rdcnn_batch_step_record": [_P, _LL, _P],
+    "rdcnn_batch_set_adjoint_kernel": [_P, _I, _I, _I],
+    "rdcnn_batch_adjoint": [_P, _P, _LL, _P, _P, ctypes.c_uint, _P],
     "rdcnn_batch_destroy": [_P],
 }
 for _name, _args in _SIGS.items():

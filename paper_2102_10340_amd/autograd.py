@@ -170,3 +170,87 @@ def simulate(x, theta, T, bc="zeroflux", ka=1.0, S=0, grads=None):
 def simulate_state(u0, v0, theta, T, bc="zeroflux", S=0, grads=None):
     """Differentiable T-step run from (u0, v0); returns (u_T, v_T)."""
     return RDCNNStateFunction.apply(u0, v0, theta, T, bc, S, None, grad_mask(grads))
+
+
+# ---------------------------------------------------------------- batches
+
+class RDCNNBatchFunction(torch.autograd.Function):
+    """(theta, x_1 .. x_n) -> (u_T,1, v_T,1, ..., u_T,n, v_T,n) of a batch,
+    u_0 = v_0 = ka x_i.  theta is [8] (shared by every instance) or [n, 8] (one
+    gene per instance).  The forward records the whole packed trajectory when it
+    fits a quarter of the free memory (else a checkpoint every S steps); the
+    backward runs the batched adjoint kernel.  Separate outputs per instance
+    keep autograd from forming a full-size gradient per instance."""
+
+    @staticmethod
+    def forward(ctx, theta, T: int, bc: str, ka: float, S: int, mask: int, *xs):
+        from .batch import Batch
+        xs = [x.detach().contiguous() for x in xs]
+        n = len(xs)
+        th = theta.detach().to("cpu", torch.float64)
+        if th.dim() == 1:
+            genes = [dict(zip(PARAM_FIELDS, th.tolist()))] * n
+        elif tuple(th.shape) == (n, 8):
+            genes = [dict(zip(PARAM_FIELDS, th[i].tolist())) for i in range(n)]
+        else:
+            raise ValueError("theta must be [8] or [n, 8]")
+        b = Batch(xs, genes, bc, ka)
+        dev = xs[0].device
+        T = int(T)
+        if S == 0:
+            free, _ = torch.cuda.mem_get_info(dev)
+            S = -1 if 4 * b.total * max(T, 1) <= free // 4 else max(1, math.ceil(math.sqrt(T)))
+        if S < 0:
+            store = torch.empty((max(T, 1), b.total), dtype=torch.float32, device=dev)
+            b.step_record(T, store)
+            nseg = 0
+        else:
+            nseg = -(-T // S) if T > 0 else 0
+            store = torch.empty((max(nseg, 1), b.total), dtype=torch.float32, device=dev)
+            for k in range(nseg):
+                store[k].copy_(b.current())
+                b.step(min(S, T - k * S))
+        outs = []
+        for i in range(n):
+            st = b.state(i)
+            outs += [st[0].clone(), st[1].clone()]
+        ctx.b, ctx.store, ctx.nseg, ctx.T, ctx.S, ctx.ka, ctx.mask = b, store, nseg, T, S, ka, mask
+        ctx.theta_meta = (theta.dtype, theta.device, theta.dim())
+        return tuple(outs)
+
+    @staticmethod
+    def backward(ctx, *gouts):
+        b, T, S = ctx.b, ctx.T, ctx.S
+        adj = torch.zeros(b.total, dtype=torch.float32, device=b.device)
+        for i in range(len(b)):
+            a = b.view(adj, i)
+            for layer in range(2):
+                gg = gouts[2 * i + layer]
+                if gg is not None:
+                    a[layer].copy_(gg)
+        tmp = torch.empty_like(adj)
+        dtheta = torch.zeros((len(b), 8), dtype=torch.float64, device=adj.device)
+        if S < 0:
+            b.adjoint(ctx.store, T, adj, tmp, ctx.mask, dtheta)
+        else:
+            seg = torch.empty((min(S, max(T, 1)), b.total), dtype=torch.float32, device=adj.device)
+            for k in range(ctx.nseg - 1, -1, -1):
+                L = min(S, T - k * S)
+                b.write_state(ctx.store[k])
+                b.step_record(L, seg)
+                b.adjoint(seg, L, adj, tmp, ctx.mask, dtheta)
+        gxs = [init_backward(b.view(adj, i), ctx.ka) for i in range(len(b))]
+        b.close()
+        dt, dd, dim = ctx.theta_meta
+        g = dtheta.cpu()
+        if dim == 1:  # shared parameters: sum over instances in a fixed order
+            g = g.sum(0)
+        return (g.to(device=dd, dtype=dt), None, None, None, None, None, *gxs)
+
+
+def simulate_batch(xs, theta, T, bc="zeroflux", ka=1.0, S=0, grads=None):
+    """Differentiable T-step run of a batch of grids (any sizes) in one go;
+    returns [(u_T, v_T) for each x].  theta: [8] shared or [n, 8] per instance;
+    grads: parameter names whose gradients are formed (default all)."""
+    out = RDCNNBatchFunction.apply(theta, int(T), bc, float(ka), int(S), grad_mask(grads), *xs)
+    return [(out[2 * i], out[2 * i + 1]) for i in range(len(xs))]

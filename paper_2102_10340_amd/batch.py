@@ -19,6 +19,16 @@ def _stream_handle(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
+def packed_layout(shapes):
+    """Float offsets of each instance's [2, R, C] state in a packed buffer
+    (256-byte aligned) and the buffer's length."""
+    offs, pos = [], 0
+    for (R, C) in shapes:
+        offs.append(pos)
+        pos += -(-2 * R * C // ALIGN) * ALIGN
+    return offs, pos
+
+
 class Batch:
     """Instances given by initial images ``xs`` (2-D float32 CUDA tensors, any
     sizes) and one gene per instance; shared boundary rule and k_a.  The states
@@ -31,11 +41,10 @@ class Batch:
         self.bc = bc
         self.shapes = [(int(x.shape[0]), int(x.shape[1])) for x in xs]
         n = len(xs)
-        offs, xoffs, pos, xpos = [], [], 0, 0
+        offs, pos = packed_layout(self.shapes)
+        xoffs, xpos = [], 0
         for (R, C) in self.shapes:
-            offs.append(pos)
             xoffs.append(xpos)
-            pos += -(-2 * R * C // ALIGN) * ALIGN
             xpos += R * C
         self.offsets = offs
         self.total = pos
@@ -83,6 +92,48 @@ class Batch:
             if b.data_ptr() == p.value:
                 return b
         raise RuntimeError("current buffer not found")
+
+    def write_state(self, packed: torch.Tensor) -> None:
+        """Replace the current packed state (float32 [total] on the device)."""
+        if packed.dtype != torch.float32 or packed.numel() < self.total or not packed.is_contiguous():
+            raise ValueError("packed state must be contiguous float32 of the batch's size")
+        self._keep = packed
+        check(lib.rdcnn_batch_write_state(self._h, packed.data_ptr()))
+
+    def step_record(self, T: int, traj: torch.Tensor) -> "Batch":
+        """Advance T steps, writing the packed state each step starts from into
+        traj[q] (float32 [>= T, total], contiguous)."""
+        if T > 0 and (traj.dtype != torch.float32 or not traj.is_contiguous() or traj.dim() != 2
+                      or traj.shape[0] < T or traj.shape[1] != self.total):
+            raise ValueError("traj must be contiguous float32 [>= T, total]")
+        check(lib.rdcnn_batch_step_record(self._h, int(T), traj.data_ptr() if T > 0 else None))
+        return self
+
+    def set_adjoint_kernel(self, depth: int = 0, cols_per_lane: int = 0, seg_rows: int = 0) -> None:
+        check(lib.rdcnn_batch_set_adjoint_kernel(self._h, int(depth), int(cols_per_lane),
+                                                 int(seg_rows)))
+
+    def adjoint(self, traj: torch.Tensor, S: int, adj: torch.Tensor, adj_tmp: torch.Tensor,
+                mask: int, dtheta: torch.Tensor) -> None:
+        """Reverse pass through the S steps recorded in traj[0..S-1] for every
+        instance: adj (packed) goes from dJ/ds after to dJ/ds before; per-instance
+        parameter gradients are added to dtheta (float64 [n, 8])."""
+        for t in (adj, adj_tmp):
+            if t.dtype != torch.float32 or t.numel() < self.total or not t.is_contiguous():
+                raise ValueError("adj buffers must be contiguous float32 of the batch's size")
+        if dtheta.dtype != torch.float64 or tuple(dtheta.shape) != (len(self), 8) or not dtheta.is_contiguous():
+            raise ValueError("dtheta must be contiguous float64 [n, 8]")
+        if S > 0 and (traj.dim() != 2 or traj.shape[0] < S or traj.shape[1] != self.total):
+            raise ValueError("traj must be [>= S, total]")
+        check(lib.rdcnn_batch_adjoint(self._h, traj.data_ptr() if S > 0 else None, int(S),
+                                      adj.data_ptr(), adj_tmp.data_ptr(), int(mask) & 0xFF,
+                                      dtheta.data_ptr()))
+
+    def view(self, packed: torch.Tensor, i: int) -> torch.Tensor:
+        """View [2, R, C] of instance i in a packed tensor of this batch's layout."""
+        R, C = self.shapes[i]
+        o = self.offsets[i]
+        return packed[o:o + 2 * R * C].view(2, R, C)
 
     def snapshot(self) -> torch.Tensor:
         """A copy of the current packed state (for the change statistics)."""

@@ -35,7 +35,8 @@ struct AdjArgs {
     TileArgs t;
     const float *in;      // (lam, mu) of level 0, [2][R][C]
     float *out;           // (lam, mu) after KB reverse steps
-    const float *states;  // the KB states this pass reads, oldest first, [KB][2][R][C]
+    const float *states;    // the KB states this pass reads, oldest first
+    unsigned state_stride;  // bytes from one state to the next ([KB][2][R][C]: 8*R*C)
     Gene g;
     double *partial;      // [>= ntiles][NSUM], accumulated
 };
@@ -51,7 +52,8 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &
     const unsigned rowb = 4u * (unsigned)C;
     const Buf il(A.in, pbytes), im(A.in + (size_t)R * C, pbytes);
     const Buf ol(A.out, pbytes), om(A.out + (size_t)R * C, pbytes);
-    const Buf sb(A.states, 2u * (unsigned)KB * pbytes);
+    const unsigned sstride = A.state_stride;
+    const Buf sb(A.states, (unsigned)(KB - 1) * sstride + 2u * pbytes);
     const Gene g = A.g;
     const float c3k = 3.0f * g.k3;
     const float epsb = g.eps * g.b;
@@ -159,7 +161,7 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &
             // i works from it = 2i+2 to n_real-1 and reads state KB-1-i); its
             // slot held the row used one iteration ago.
             if (it + 2 >= 2 * i + 2 && it + 2 < n_real) {
-                const unsigned o = 2u * (unsigned)(KB - 1 - i) * pbytes + roff(m + 2);
+                const unsigned o = (unsigned)(KB - 1 - i) * sstride + roff(m + 2);
                 load_row<CPL, FAST>(sb, o, t, su[i][sl.ps]);
                 load_row<CPL, FAST>(sb, o + pbytes, t, sv[i][sl.ps]);
             }
@@ -204,6 +206,105 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs A)
     }
 }
 
+// The eight gradients (order dt, a, b, eps, c, k3, Du, Dv) from the eight
+// sums, added to dtheta; gradients outside the mask were not summed and are
+// set to NaN.
+__device__ void add_grads(const double *S, const Gene &g, unsigned mask, double *dtheta)
+{
+    const double dt = g.dt, a = g.a, b = g.b, eps = g.eps, c = g.c, k3 = g.k3;
+    const double Du = g.Du, Dv = g.Dv;
+    const double LLU = S[S_LLU], LMV = S[S_LMV], LU = S[S_LU], LU3 = S[S_LU3], LV = S[S_LV];
+    const double MU = S[S_MU], MV = S[S_MV], M = S[S_M];
+    const double res = MU - b * MV + a * M;  // <mu', u - b v + a>
+    double d[8];
+    d[0] = c * LU - k3 * LU3 - LV - eps * res + Du * LLU + Dv * LMV;  // dt
+    d[1] = -dt * eps * M;                                             // a
+    d[2] = dt * eps * MV;                                             // b
+    d[3] = -dt * res;                                                 // eps
+    d[4] = dt * LU;                                                   // c
+    d[5] = -dt * LU3;                                                 // k3
+    d[6] = dt * LLU;                                                  // Du
+    d[7] = dt * LMV;                                                  // Dv
+    for (int q = 0; q < 8; ++q) dtheta[q] = (mask >> q) & 1u ? dtheta[q] + d[q] : __builtin_nan("");
+}
+
+// ---------------------------------------------------------------- batches
+//
+// The reverse pass over a batch: the same body over a flat tile list covering
+// all instances (each tile reads its instance's offset, size and gene).  The
+// trajectory holds whole packed batch states, state_stride bytes apart; each
+// tile's sums go to its own slot, and batch_adjoint_finish_kernel folds every
+// instance's tiles, in a fixed order, into that instance's gradients.
+struct BatchAdjArgs {
+    const BatchTile *tiles;
+    const BatchInst *insts;
+    int ntiles;
+    const float *in;        // packed (lam, mu) of level 0
+    float *out;             // packed (lam, mu) after KB reverse steps
+    const float *states;    // packed state q_top-KB+1 of the trajectory
+    unsigned state_stride;  // bytes between packed states
+    int bc, wout, kpad;
+    double *partial;        // [ntiles][NSUM], accumulated
+};
+
+template <int CPL, int KB, bool LAMS>
+__global__ __launch_bounds__(64) void batch_adjoint_kernel(BatchAdjArgs B)
+{
+    const int id = blockIdx.x;
+    if (id >= B.ntiles) return;
+    const BatchTile bt = B.tiles[id];
+    const BatchInst in = B.insts[bt.inst];
+    AdjArgs A;
+    A.t.R = in.R;
+    A.t.C = in.C;
+    A.t.bc = B.bc;
+    A.t.wout = B.wout;
+    A.t.kpad = B.kpad;
+    A.t.h = 0;
+    A.t.nsegs = 0;
+    A.t.ntiles = 0;
+    A.t.per_xcd = 0;
+    A.t.vec_ok = (in.C % CPL) == 0;
+    A.in = B.in + in.off;
+    A.out = B.out + in.off;
+    A.states = B.states + in.off;
+    A.state_stride = B.state_stride;
+    A.g = in.g;
+    A.partial = B.partial;
+    Tile<CPL> t;
+    t.setup(A.t, id, bt.x0, bt.y0, bt.y1);
+    if (t.fast) {
+        if (t.y0 >= KB && t.y1 + KB <= in.R)
+            adjoint_body<CPL, KB, true, true, LAMS>(A, t);
+        else
+            adjoint_body<CPL, KB, true, false, LAMS>(A, t);
+    } else {
+        adjoint_body<CPL, KB, false, false, LAMS>(A, t);
+    }
+}
+
+// One thread per instance: sum the partials of its tiles (tile ids
+// tiles_of[first[i] .. first[i+1]), ascending) and add its gradients to
+// dtheta[8 i ..].
+__global__ __launch_bounds__(256) void batch_adjoint_finish_kernel(const double *partial,
+                                                                   const int *first,
+                                                                   const int *tiles_of,
+                                                                   const BatchInst *insts, int n,
+                                                                   unsigned mask, double *dtheta)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double S[NSUM];
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) S[k] = 0.0;
+    for (int q = first[i]; q < first[i + 1]; ++q) {
+        const double *p = partial + (size_t)tiles_of[q] * NSUM;
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k) S[k] += p[k];
+    }
+    add_grads(S, insts[i].g, mask, dtheta + 8 * (size_t)i);
+}
+
 __global__ __launch_bounds__(256) void zero_kernel(double *p, long long n)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -212,7 +313,7 @@ __global__ __launch_bounds__(256) void zero_kernel(double *p, long long n)
 }
 
 // One workgroup: sums the per-tile partials in a fixed order and adds the
-// gradients (order dt, a, b, eps, c, k3, Du, Dv) to dtheta.
+// gradients to dtheta.
 __global__ __launch_bounds__(256) void adjoint_finish_kernel(const double *partial, int ntiles,
                                                              Gene g, unsigned mask, double *dtheta)
 {
@@ -233,23 +334,10 @@ __global__ __launch_bounds__(256) void adjoint_finish_kernel(const double *parti
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double dt = g.dt, a = g.a, b = g.b, eps = g.eps, c = g.c, k3 = g.k3;
-        const double Du = g.Du, Dv = g.Dv;
-        const double LLU = red[S_LLU][0], LMV = red[S_LMV][0], LU = red[S_LU][0];
-        const double LU3 = red[S_LU3][0], LV = red[S_LV][0], MU = red[S_MU][0];
-        const double MV = red[S_MV][0], M = red[S_M][0];
-        const double res = MU - b * MV + a * M;  // <mu', u - b v + a>
-        double d[8];
-        d[0] = c * LU - k3 * LU3 - LV - eps * res + Du * LLU + Dv * LMV;  // dt
-        d[1] = -dt * eps * M;                                             // a
-        d[2] = dt * eps * MV;                                             // b
-        d[3] = -dt * res;                                                 // eps
-        d[4] = dt * LU;                                                   // c
-        d[5] = -dt * LU3;                                                 // k3
-        d[6] = dt * LLU;                                                  // Du
-        d[7] = dt * LMV;                                                  // Dv
-        // Gradients outside the mask were not summed: mark them NaN.
-        for (int q = 0; q < 8; ++q) dtheta[q] = (mask >> q) & 1u ? dtheta[q] + d[q] : __builtin_nan("");
+        double S[NSUM];
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k) S[k] = red[k][0];
+        add_grads(S, g, mask, dtheta);
     }
 }
 
@@ -303,9 +391,65 @@ hipError_t launch_adjoint(const float *in, float *out, const float *states, long
     a.in = in;
     a.out = out;
     a.states = states + (q_top - geom.depth + 1) * 2LL * R * C;
+    a.state_stride = 8u * (unsigned)R * (unsigned)C;
     a.g = g;
     a.partial = partial;
     hipLaunchKernelGGL(f, dim3((unsigned)(8 * geom.per_xcd)), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+namespace {
+
+using BatchAdjFn = void (*)(BatchAdjArgs);
+
+template <bool LAMS>
+BatchAdjFn pick_batch_adj(int cpl, int depth)
+{
+    if (cpl == 1) {
+        if (depth == 2) return &batch_adjoint_kernel<1, 2, LAMS>;
+        if (depth == 4) return &batch_adjoint_kernel<1, 4, LAMS>;
+        if (depth == 8) return &batch_adjoint_kernel<1, 8, LAMS>;
+        if (depth == 1) return &batch_adjoint_kernel<1, 1, LAMS>;
+    } else if (cpl == 2) {
+        if (depth == 2) return &batch_adjoint_kernel<2, 2, LAMS>;
+        if (depth == 4) return &batch_adjoint_kernel<2, 4, LAMS>;
+        if (depth == 8) return &batch_adjoint_kernel<2, 8, LAMS>;
+        if (depth == 1) return &batch_adjoint_kernel<2, 1, LAMS>;
+    }
+    return nullptr;
+}
+
+}  // namespace
+
+hipError_t launch_batch_adjoint(const BatchTile *tiles, const BatchInst *insts, int ntiles,
+                                const float *in, float *out, const float *states,
+                                unsigned state_stride, int bc, int cpl, int depth, int table_depth,
+                                double *partial, bool lam_sums, hipStream_t s)
+{
+    BatchAdjFn f = lam_sums ? pick_batch_adj<true>(cpl, depth) : pick_batch_adj<false>(cpl, depth);
+    if (!f || ntiles < 1) return hipErrorInvalidValue;
+    BatchAdjArgs a;
+    a.tiles = tiles;
+    a.insts = insts;
+    a.ntiles = ntiles;
+    a.in = in;
+    a.out = out;
+    a.states = states;
+    a.state_stride = state_stride;
+    a.bc = bc;
+    a.kpad = (table_depth + cpl - 1) / cpl * cpl;  // the tile list's halo (>= depth)
+    a.wout = 64 * cpl - 2 * a.kpad;
+    a.partial = partial;
+    hipLaunchKernelGGL(f, dim3((unsigned)ntiles), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_adjoint_finish(const double *partial, const int *first, const int *tiles_of,
+                                       const BatchInst *insts, int n, unsigned mask,
+                                       double *dtheta, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_adjoint_finish_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       s, partial, first, tiles_of, insts, n, mask, dtheta);
     return hipGetLastError();
 }
 

@@ -22,10 +22,6 @@
 
 namespace rd {
 
-struct BatchTile {
-    int inst, x0, y0, y1;
-};
-
 struct BatchArgs {
     const BatchTile *tiles;
     const BatchInst *insts;
@@ -33,9 +29,11 @@ struct BatchArgs {
     const float *in;
     float *out;
     int bc, wout, kpad;
+    float *rec;           // packed trajectory, state of level 0 (REC only)
+    unsigned rec_stride;  // bytes between packed states
 };
 
-template <int CPL, int K>
+template <int CPL, int K, bool REC>
 __global__ __launch_bounds__(64) void batch_step_kernel(BatchArgs B)
 {
     const int id = blockIdx.x;
@@ -56,16 +54,17 @@ __global__ __launch_bounds__(64) void batch_step_kernel(BatchArgs B)
     A.in = B.in + in.off;
     A.out = B.out + in.off;
     A.g = in.g;
-    A.rec = nullptr;
+    A.rec = REC ? B.rec + in.off : nullptr;
+    A.rec_stride = B.rec_stride;
     Tile<CPL> t;
     t.setup(A.t, id, bt.x0, bt.y0, bt.y1);
     if (t.fast) {
         if (t.y0 >= K && t.y1 + K <= in.R)
-            stream_body<ModelFHN, CPL, K, false, true, true>(A, t);
+            stream_body<ModelFHN, CPL, K, REC, true, true>(A, t);
         else
-            stream_body<ModelFHN, CPL, K, false, true, false>(A, t);
+            stream_body<ModelFHN, CPL, K, REC, true, false>(A, t);
     } else {
-        stream_body<ModelFHN, CPL, K, false, false, false>(A, t);
+        stream_body<ModelFHN, CPL, K, REC, false, false>(A, t);
     }
 }
 
@@ -197,26 +196,33 @@ namespace {
 
 using BatchFn = void (*)(BatchArgs);
 
-template <int CPL, int... Ks>
+template <int CPL, bool REC, int... Ks>
 constexpr BatchFn pick(int k, std::integer_sequence<int, Ks...>)
 {
     BatchFn f = nullptr;
-    ((f = (k == Ks + 1) ? &batch_step_kernel<CPL, Ks + 1> : f), ...);
+    ((f = (k == Ks + 1) ? &batch_step_kernel<CPL, Ks + 1, REC> : f), ...);
     return f;
 }
 
 }  // namespace
 
 hipError_t launch_batch(const BatchTile *tiles, const BatchInst *insts, int ntiles,
-                        const float *in, float *out, int bc, int cpl, int depth, hipStream_t s)
+                        const float *in, float *out, int bc, int cpl, int depth, hipStream_t s,
+                        float *rec, unsigned rec_stride)
 {
     BatchFn f = nullptr;
-    if (cpl == 4)
-        f = pick<4>(depth, std::make_integer_sequence<int, kMaxDepthCpl4>{});
-    else if (cpl == 2)
-        f = pick<2>(depth, std::make_integer_sequence<int, kMaxDepthCpl2>{});
-    else if (cpl == 1)
-        f = pick<1>(depth, std::make_integer_sequence<int, kMaxDepthCpl1>{});
+    if (rec) {  // recording passes: cpl 1 or 2, depth <= 8
+        if (cpl == 2)
+            f = pick<2, true>(depth, std::make_integer_sequence<int, 8>{});
+        else if (cpl == 1)
+            f = pick<1, true>(depth, std::make_integer_sequence<int, 8>{});
+    } else if (cpl == 4) {
+        f = pick<4, false>(depth, std::make_integer_sequence<int, kMaxDepthCpl4>{});
+    } else if (cpl == 2) {
+        f = pick<2, false>(depth, std::make_integer_sequence<int, kMaxDepthCpl2>{});
+    } else if (cpl == 1) {
+        f = pick<1, false>(depth, std::make_integer_sequence<int, kMaxDepthCpl1>{});
+    }
     if (!f || ntiles < 1) return hipErrorInvalidValue;
     BatchArgs a;
     a.tiles = tiles;
@@ -227,6 +233,8 @@ hipError_t launch_batch(const BatchTile *tiles, const BatchInst *insts, int ntil
     a.bc = bc;
     a.kpad = (depth + cpl - 1) / cpl * cpl;
     a.wout = 64 * cpl - 2 * a.kpad;
+    a.rec = rec;
+    a.rec_stride = rec_stride;
     hipLaunchKernelGGL(f, dim3((unsigned)ntiles), dim3(64), 0, s, a);
     return hipGetLastError();
 }
@@ -267,6 +275,14 @@ struct rdcnn_batch {
     int *stat_first;
     double *stat_partial;
     int stat_nchunks;
+    long long total;                 // floats in one packed state buffer
+    std::vector<TileTable> rec_tables;  // recording passes (every instance streamed)
+    int rec_cpl;
+    // reverse pass: one tile list (cut for adj_depth), per-instance tile lists
+    TileTable adj_table;
+    int adj_cpl, adj_depth, adj_seg;
+    int *adj_first, *adj_tiles_of;
+    double *adj_partial;
 };
 
 #define bfail(...) rd::set_error(__VA_ARGS__)
@@ -278,6 +294,9 @@ void free_tables(rdcnn_batch *b)
     for (TileTable &t : b->tables)
         if (t.dev) (void)hipFree(t.dev);
     b->tables.clear();
+    for (TileTable &t : b->rec_tables)
+        if (t.dev) (void)hipFree(t.dev);
+    b->rec_tables.clear();
 }
 
 void drop_graph(rdcnn_batch *b)
@@ -381,21 +400,18 @@ void batch_config(const rdcnn_batch *b, int *cpl, int *depth, int *seg)
     *seg = b->seg_rows ? b->seg_rows : 128;
 }
 
-// Tile list for one pass depth: every instance cut into strips of wout output
-// columns and segments of `seg` rows, longest tiles first.
-int table_for(rdcnn_batch *b, int cpl, int depth, int seg, const TileTable **out)
+// Tile list for one pass depth: every instance (but those run in LDS, if
+// skip_lds) cut into strips of wout output columns and segments of `seg` rows,
+// longest tiles first.
+int build_tiles(const rdcnn_batch *b, int cpl, int depth, int seg, bool skip_lds,
+                std::vector<rd::BatchTile> &tiles)
 {
-    for (const TileTable &t : b->tables)
-        if (t.depth == depth) {
-            *out = &t;
-            return RDCNN_OK;
-        }
     const int kpad = (depth + cpl - 1) / cpl * cpl;
     const int wout = 64 * cpl - 2 * kpad;
     if (wout <= 0) return bfail(RDCNN_EINVAL, "batch: depth %d too large for cpl %d", depth, cpl);
-    std::vector<rd::BatchTile> tiles;
+    tiles.clear();
     for (int i = 0; i < b->n; ++i) {
-        if (b->in_lds[i]) continue;
+        if (skip_lds && b->in_lds[i]) continue;
         const int R = b->R[i], C = b->C[i];
         const int h = seg < R ? seg : R;
         for (int sx = 0; sx * wout < C; ++sx)
@@ -409,29 +425,111 @@ int table_for(rdcnn_batch *b, int cpl, int depth, int seg, const TileTable **out
             }
     }
     if (tiles.size() >= (1u << 31)) return bfail(RDCNN_EINVAL, "batch: too many tiles");
-    if (tiles.empty()) {  // every instance runs in LDS
-        TileTable t;
-        t.depth = depth;
-        b->tables.push_back(t);
-        *out = &b->tables.back();
-        return RDCNN_OK;
-    }
     std::stable_sort(tiles.begin(), tiles.end(), [](const rd::BatchTile &a, const rd::BatchTile &c) {
         return (a.y1 - a.y0) > (c.y1 - c.y0);
     });
-    TileTable t;
+    return RDCNN_OK;
+}
+
+// Upload a tile list into t (t.dev stays null for an empty list).
+int upload_tiles(const std::vector<rd::BatchTile> &tiles, int depth, TileTable &t)
+{
     t.depth = depth;
     t.ntiles = (int)tiles.size();
+    t.dev = nullptr;
+    if (tiles.empty()) return RDCNN_OK;
     hipError_t e = hipMalloc((void **)&t.dev, sizeof(rd::BatchTile) * tiles.size());
     if (e != hipSuccess) return bfail(RDCNN_ENOMEM, "batch: tile table: %s", hipGetErrorString(e));
     e = hipMemcpy(t.dev, tiles.data(), sizeof(rd::BatchTile) * tiles.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(t.dev);
+        t.dev = nullptr;
         return bfail(RDCNN_EHIP, "batch: tile table upload: %s", hipGetErrorString(e));
     }
-    b->tables.push_back(t);
-    *out = &b->tables.back();
     return RDCNN_OK;
+}
+
+// The table of `depth` in a set (built on first use).
+int table_in(rdcnn_batch *b, std::vector<TileTable> &set, int cpl, int depth, int seg,
+             bool skip_lds, const TileTable **out)
+{
+    for (const TileTable &t : set)
+        if (t.depth == depth) {
+            *out = &t;
+            return RDCNN_OK;
+        }
+    std::vector<rd::BatchTile> tiles;
+    int rc = build_tiles(b, cpl, depth, seg, skip_lds, tiles);
+    if (rc != RDCNN_OK) return rc;
+    TileTable t;
+    rc = upload_tiles(tiles, depth, t);
+    if (rc != RDCNN_OK) return rc;
+    set.push_back(t);
+    *out = &set.back();
+    return RDCNN_OK;
+}
+
+int table_for(rdcnn_batch *b, int cpl, int depth, int seg, const TileTable **out)
+{
+    return table_in(b, b->tables, cpl, depth, seg, true, out);
+}
+
+void free_adj(rdcnn_batch *b)
+{
+    if (b->adj_table.dev) (void)hipFree(b->adj_table.dev);
+    if (b->adj_first) (void)hipFree(b->adj_first);
+    if (b->adj_tiles_of) (void)hipFree(b->adj_tiles_of);
+    if (b->adj_partial) (void)hipFree(b->adj_partial);
+    b->adj_table = TileTable();
+    b->adj_first = b->adj_tiles_of = nullptr;
+    b->adj_partial = nullptr;
+}
+
+// The reverse pass's tile list (every instance, cut for adj_depth), its
+// per-instance tile lists and the per-tile partial buffer.
+int setup_adj(rdcnn_batch *b)
+{
+    free_adj(b);
+    std::vector<rd::BatchTile> tiles;
+    int rc = build_tiles(b, b->adj_cpl, b->adj_depth, b->adj_seg, false, tiles);
+    if (rc != RDCNN_OK) return rc;
+    std::vector<int> first(b->n + 1, 0), tiles_of(tiles.size());
+    for (const rd::BatchTile &t : tiles) ++first[t.inst + 1];
+    for (int i = 0; i < b->n; ++i) first[i + 1] += first[i];
+    {
+        std::vector<int> pos(first.begin(), first.end() - 1);
+        for (int k = 0; k < (int)tiles.size(); ++k) tiles_of[pos[tiles[k].inst]++] = k;
+    }
+    rc = upload_tiles(tiles, b->adj_depth, b->adj_table);
+    if (rc != RDCNN_OK) return rc;
+    hipError_t e = hipMalloc((void **)&b->adj_first, sizeof(int) * first.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&b->adj_tiles_of, sizeof(int) * (tiles_of.size() + 1));
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&b->adj_partial, sizeof(double) * rd::kAdjSums * (tiles.size() + 1));
+    if (e == hipSuccess)
+        e = hipMemcpy(b->adj_first, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !tiles_of.empty())
+        e = hipMemcpy(b->adj_tiles_of, tiles_of.data(), sizeof(int) * tiles_of.size(),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_adj(b);
+        return bfail(RDCNN_ENOMEM, "rdcnn_batch_adjoint: %s", hipGetErrorString(e));
+    }
+    return RDCNN_OK;
+}
+
+// Largest depth <= want whose passes keep one instance's span of recorded
+// states (depth-1 packed strides plus its own state) within a 4 GiB buffer
+// resource.
+int state_depth_cap(const rdcnn_batch *b, int want)
+{
+    long long maxrc = 0;
+    for (int i = 0; i < b->n; ++i)
+        if ((long long)b->R[i] * b->C[i] > maxrc) maxrc = (long long)b->R[i] * b->C[i];
+    int k = want;
+    while (k > 1 && (long long)(k - 1) * b->total * 4 + 8 * maxrc > 0xFFFFFFFFLL) --k;
+    if ((long long)8 * maxrc > 0xFFFFFFFFLL || b->total * 4 > 0xFFFFFFFFLL) return 0;
+    return k;
 }
 
 // Enqueue the launches of T steps; cur flips once per streamed launch.  The
@@ -543,6 +641,14 @@ int rdcnn_batch_create(rdcnn_batch_t *out, int n, const int *rows, const int *co
     b->stat_first = nullptr;
     b->stat_partial = nullptr;
     b->stat_nchunks = 0;
+    b->total = buf_floats;
+    b->rec_cpl = 2;
+    b->adj_table = TileTable();
+    b->adj_cpl = 2;
+    b->adj_depth = 4;
+    b->adj_seg = 64;
+    b->adj_first = b->adj_tiles_of = nullptr;
+    b->adj_partial = nullptr;
     b->use_lds = 1;
     b->lds_ids_dev = nullptr;
     b->lds_count = b->lds_frame = 0;
@@ -576,6 +682,113 @@ int rdcnn_batch_create(rdcnn_batch_t *out, int n, const int *rows, const int *co
         return rc;
     }
     *out = b;
+    return RDCNN_OK;
+}
+
+int rdcnn_batch_write_state(rdcnn_batch_t b, const float *packed)
+{
+    if (!b || !packed) return bfail(RDCNN_EINVAL, "rdcnn_batch_write_state: NULL argument");
+    hipError_t e = hipMemcpyAsync(b->buf[b->cur], packed, sizeof(float) * b->total,
+                                  hipMemcpyDeviceToDevice, b->stream);
+    if (e != hipSuccess)
+        return bfail(RDCNN_EHIP, "rdcnn_batch_write_state: %s", hipGetErrorString(e));
+    return RDCNN_OK;
+}
+
+int rdcnn_batch_step_record(rdcnn_batch_t b, long long T, float *traj)
+{
+    if (!b) return bfail(RDCNN_EINVAL, "rdcnn_batch_step_record: NULL handle");
+    if (T < 0) return bfail(RDCNN_EINVAL, "rdcnn_batch_step_record: T = %lld < 0", T);
+    if (T == 0) return RDCNN_OK;
+    if (!traj) return bfail(RDCNN_EINVAL, "rdcnn_batch_step_record: NULL trajectory");
+    int cpl, depth, seg;
+    batch_config(b, &cpl, &depth, &seg);
+    if (cpl > 2) cpl = 2;  // recording passes exist for 1 or 2 columns per lane
+    if (depth > 8) depth = 8;
+    depth = state_depth_cap(b, depth);
+    if (depth < 1)
+        return bfail(RDCNN_EINVAL, "rdcnn_batch_step_record: packed state too large to record");
+    if (cpl != b->rec_cpl) {
+        for (TileTable &t : b->rec_tables)
+            if (t.dev) (void)hipFree(t.dev);
+        b->rec_tables.clear();
+        b->rec_cpl = cpl;
+    }
+    long long q = 0;
+    while (T > 0) {
+        const int k = (int)(T < depth ? T : depth);
+        const TileTable *t = nullptr;
+        int rc = table_in(b, b->rec_tables, cpl, k, seg, false, &t);
+        if (rc != RDCNN_OK) return rc;
+        hipError_t e = rd::launch_batch(t->dev, b->insts_dev, t->ntiles, b->buf[b->cur],
+                                        b->buf[1 - b->cur], b->bc, cpl, k, b->stream,
+                                        traj + q * b->total, (unsigned)(4 * b->total));
+        if (e != hipSuccess)
+            return bfail(RDCNN_EHIP, "rdcnn_batch_step_record: %s", hipGetErrorString(e));
+        b->cur = 1 - b->cur;
+        q += k;
+        T -= k;
+    }
+    return RDCNN_OK;
+}
+
+int rdcnn_batch_set_adjoint_kernel(rdcnn_batch_t b, int depth, int cols_per_lane, int seg_rows)
+{
+    if (!b) return bfail(RDCNN_EINVAL, "rdcnn_batch_set_adjoint_kernel: NULL handle");
+    if (depth == 0) depth = 4;
+    if (cols_per_lane == 0) cols_per_lane = 2;
+    if (seg_rows == 0) seg_rows = 64;
+    if (depth != 1 && depth != 2 && depth != 4 && depth != 8)
+        return bfail(RDCNN_EINVAL, "rdcnn_batch_set_adjoint_kernel: depth %d not in {1,2,4,8}", depth);
+    if (cols_per_lane != 1 && cols_per_lane != 2)
+        return bfail(RDCNN_EINVAL, "rdcnn_batch_set_adjoint_kernel: cols_per_lane %d not in {1,2}",
+                     cols_per_lane);
+    if (seg_rows < 1) return bfail(RDCNN_EINVAL, "rdcnn_batch_set_adjoint_kernel: seg_rows < 1");
+    free_adj(b);
+    b->adj_depth = depth;
+    b->adj_cpl = cols_per_lane;
+    b->adj_seg = seg_rows;
+    return RDCNN_OK;
+}
+
+int rdcnn_batch_adjoint(rdcnn_batch_t b, const float *traj, long long S, float *adj,
+                        float *adj_tmp, unsigned mask, double *dtheta)
+{
+    if (!b) return bfail(RDCNN_EINVAL, "rdcnn_batch_adjoint: NULL handle");
+    if (S < 0) return bfail(RDCNN_EINVAL, "rdcnn_batch_adjoint: S = %lld < 0", S);
+    if (!adj || !adj_tmp || !dtheta || (S > 0 && !traj))
+        return bfail(RDCNN_EINVAL, "rdcnn_batch_adjoint: NULL buffer");
+    if (adj == adj_tmp) return bfail(RDCNN_EINVAL, "rdcnn_batch_adjoint: adj and adj_tmp alias");
+    if (state_depth_cap(b, b->adj_depth) < b->adj_depth)
+        return bfail(RDCNN_EINVAL, "rdcnn_batch_adjoint: packed state too large for depth %d",
+                     b->adj_depth);
+    if (!b->adj_partial) {
+        const int rc = setup_adj(b);
+        if (rc != RDCNN_OK) return rc;
+    }
+    const int ntiles = b->adj_table.ntiles;
+    hipError_t e = rd::launch_zero(b->adj_partial, (long long)rd::kAdjSums * (ntiles + 1), b->stream);
+    const bool lam_sums = (mask & ((1u << 0) | (1u << 4) | (1u << 5))) != 0;
+    float *src = adj, *dst = adj_tmp;
+    long long top = S - 1;  // state the next reverse step steps back over
+    while (e == hipSuccess && top >= 0 && ntiles > 0) {
+        int k = b->adj_depth;
+        while (k > 1 && k > top + 1) k >>= 1;
+        e = rd::launch_batch_adjoint(b->adj_table.dev, b->insts_dev, ntiles, src, dst,
+                                     traj + (top - k + 1) * b->total, (unsigned)(4 * b->total),
+                                     b->bc, b->adj_cpl, k, b->adj_depth, b->adj_partial, lam_sums,
+                                     b->stream);
+        float *x = src;
+        src = dst;
+        dst = x;
+        top -= k;
+    }
+    if (e == hipSuccess && src != adj)
+        e = hipMemcpyAsync(adj, src, sizeof(float) * b->total, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess)
+        e = rd::launch_batch_adjoint_finish(b->adj_partial, b->adj_first, b->adj_tiles_of,
+                                            b->insts_dev, b->n, mask, dtheta, b->stream);
+    if (e != hipSuccess) return bfail(RDCNN_EHIP, "rdcnn_batch_adjoint: %s", hipGetErrorString(e));
     return RDCNN_OK;
 }
 
@@ -704,6 +917,7 @@ int rdcnn_batch_destroy(rdcnn_batch_t b)
     free_tables(b);
     free_lds(b);
     free_stats(b);
+    free_adj(b);
     if (b->insts_dev) (void)hipFree(b->insts_dev);
     delete b;
     return RDCNN_OK;

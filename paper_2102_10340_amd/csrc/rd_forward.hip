@@ -178,6 +178,7 @@ hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, cons
     a.out = out;
     a.g = g;
     a.rec = rec ? rec + rec_q0 * 2LL * R * C : nullptr;
+    a.rec_stride = 8u * (unsigned)R * (unsigned)C;
     hipLaunchKernelGGL(f, dim3((unsigned)(8 * geom.per_xcd)), dim3(64), 0, s, a);
     return hipGetLastError();
 }

@@ -24,7 +24,8 @@ struct StreamArgsT {
     const float *in;
     float *out;
     typename M::Params g;
-    float *rec;  // recording: level j of the pass goes to state j of rec (null: off)
+    float *rec;           // recording: level j of the pass goes to state j of rec (null: off)
+    unsigned rec_stride;  // bytes from one recorded state to the next
 };
 using StreamArgs = StreamArgsT<ModelFHN>;
 
@@ -38,8 +39,9 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
     const unsigned rowb = 4u * (unsigned)C;
     const Buf iu(A.in, pbytes), iv(A.in + (size_t)R * C, pbytes);
     const Buf ou(A.out, pbytes), ov(A.out + (size_t)R * C, pbytes);
-    // K recorded states, u plane then v plane each: state j at byte 2*j*pbytes.
-    const Buf rb(REC ? A.rec : A.in, REC ? 2u * (unsigned)K * pbytes : 0u);
+    // K recorded states, u plane then v plane each: state j at byte j*rec_stride.
+    const unsigned rstride = A.rec_stride;
+    const Buf rb(REC ? A.rec : A.in, REC ? (unsigned)(K - 1) * rstride + 2u * pbytes : 0u);
     const typename M::Params g = A.g;
     const int y0 = t.y0, y1 = t.y1;
 
@@ -143,7 +145,7 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
             if (REC && j + 1 < K && it >= 2 * j + 2 && it < n_real) {
                 const int m = rbase + it - j - 1;  // level-(j+1) row just made
                 if (m >= y0 && m < y1) {
-                    const unsigned o = 2u * (unsigned)(j + 1) * pbytes + 4u * (unsigned)m * C;
+                    const unsigned o = (unsigned)(j + 1) * rstride + 4u * (unsigned)m * C;
                     store_row<CPL, FAST>(rb, o, C, t, bu[j + 1][sl.cs]);
                     store_row<CPL, FAST>(rb, o + pbytes, C, t, bv[j + 1][sl.cs]);
                 }

@@ -101,10 +101,32 @@ struct BatchInst {
     Gene g;
 };
 
+// One tile of a batch's flat tile list: instance, first extended column and
+// output rows [y0, y1).
+struct BatchTile {
+    int inst, x0, y0, y1;
+};
+
 // One launch of the batched kernel: `depth` steps for every tile of the list.
-struct BatchTile;
+// With rec, the states the pass steps from also go to the packed trajectory:
+// level j of instance i to rec + j * rec_stride bytes + its offset (recording
+// passes: cpl 1 or 2, depth <= 8).
 hipError_t launch_batch(const BatchTile *tiles, const BatchInst *insts, int ntiles,
-                        const float *in, float *out, int bc, int cpl, int depth, hipStream_t s);
+                        const float *in, float *out, int bc, int cpl, int depth, hipStream_t s,
+                        float *rec = nullptr, unsigned rec_stride = 0);
+
+// Batched reverse pass: `depth` (1, 2, 4 or 8) reverse steps for every tile,
+// cpl 1 or 2; states = packed state q_top-depth+1, state_stride bytes apart.
+// The tile list was cut for table_depth >= depth (its halo is used as is).
+hipError_t launch_batch_adjoint(const BatchTile *tiles, const BatchInst *insts, int ntiles,
+                                const float *in, float *out, const float *states,
+                                unsigned state_stride, int bc, int cpl, int depth, int table_depth,
+                                double *partial, bool lam_sums, hipStream_t s);
+// Per-instance gradients from the per-tile partials (tiles of instance i:
+// tiles_of[first[i] .. first[i+1])), added to dtheta[8 i ..].
+hipError_t launch_batch_adjoint_finish(const double *partial, const int *first, const int *tiles_of,
+                                       const BatchInst *insts, int n, unsigned mask,
+                                       double *dtheta, hipStream_t s);
 
 // All T steps of `count` small instances (indices ids), each held in one
 // workgroup's LDS (frame_cells = largest (R+2)*(C+2)).

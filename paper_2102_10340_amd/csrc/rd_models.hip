@@ -76,6 +76,7 @@ hipError_t launch_as(const float *in, float *out, int R, int C, int bc,
     a.out = out;
     a.g = p;
     a.rec = nullptr;
+    a.rec_stride = 0;
     hipLaunchKernelGGL(f, dim3((unsigned)(8 * geom.per_xcd)), dim3(64), 0, s, a);
     return hipGetLastError();
 }
