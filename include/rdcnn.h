@@ -307,7 +307,9 @@ int rdcnn_batch_step_record(rdcnn_batch_t b, long long T, float *traj);
 /*
  * rdcnn_batch_set_adjoint_kernel -- pass shape of rdcnn_batch_adjoint: depth
  * (reverse steps per pass: 1, 2, 4 or 8), cols_per_lane (1 or 2), seg_rows
- * (rows per tile); 0 keeps the default (4, 2, 64).  Errors: RDCNN_EINVAL.
+ * (rows per tile); 0 keeps the default (8, 1, 128).  Passes are made shallower
+ * where one instance's span of a pass's states would pass 4 GiB.  Errors:
+ * RDCNN_EINVAL.
  */
 int rdcnn_batch_set_adjoint_kernel(rdcnn_batch_t b, int depth, int cols_per_lane, int seg_rows);
 
@@ -324,7 +326,7 @@ int rdcnn_batch_set_adjoint_kernel(rdcnn_batch_t b, int depth, int cols_per_lane
  * mask are not formed and come back NaN.  Sums are folded per instance in a
  * fixed order (deterministic).  The first call allocates the tile list and the
  * per-tile partial buffer (kept until destroy).  Errors: RDCNN_EINVAL (NULL or
- * aliased buffers, S < 0, packed state too large for the depth), RDCNN_ENOMEM,
+ * aliased buffers, S < 0, one instance's state alone above 4 GiB), RDCNN_ENOMEM,
  * RDCNN_EHIP.
  */
 int rdcnn_batch_adjoint(rdcnn_batch_t b, const float *traj, long long S, float *adj,

@@ -644,9 +644,10 @@ int rdcnn_batch_create(rdcnn_batch_t *out, int n, const int *rows, const int *co
     b->total = buf_floats;
     b->rec_cpl = 2;
     b->adj_table = TileTable();
-    b->adj_cpl = 2;
-    b->adj_depth = 4;
-    b->adj_seg = 64;
+    // reverse-pass defaults from a sweep of 64 x 1024^2 on MI355X
+    b->adj_cpl = 1;
+    b->adj_depth = 8;
+    b->adj_seg = 128;
     b->adj_first = b->adj_tiles_of = nullptr;
     b->adj_partial = nullptr;
     b->use_lds = 1;
@@ -705,6 +706,7 @@ int rdcnn_batch_step_record(rdcnn_batch_t b, long long T, float *traj)
     batch_config(b, &cpl, &depth, &seg);
     if (cpl > 2) cpl = 2;  // recording passes exist for 1 or 2 columns per lane
     if (depth > 8) depth = 8;
+    if (!b->seg_rows) seg = 64;  // recording is write-bound; shorter tiles led a sweep
     depth = state_depth_cap(b, depth);
     if (depth < 1)
         return bfail(RDCNN_EINVAL, "rdcnn_batch_step_record: packed state too large to record");
@@ -735,9 +737,9 @@ int rdcnn_batch_step_record(rdcnn_batch_t b, long long T, float *traj)
 int rdcnn_batch_set_adjoint_kernel(rdcnn_batch_t b, int depth, int cols_per_lane, int seg_rows)
 {
     if (!b) return bfail(RDCNN_EINVAL, "rdcnn_batch_set_adjoint_kernel: NULL handle");
-    if (depth == 0) depth = 4;
-    if (cols_per_lane == 0) cols_per_lane = 2;
-    if (seg_rows == 0) seg_rows = 64;
+    if (depth == 0) depth = 8;
+    if (cols_per_lane == 0) cols_per_lane = 1;
+    if (seg_rows == 0) seg_rows = 128;
     if (depth != 1 && depth != 2 && depth != 4 && depth != 8)
         return bfail(RDCNN_EINVAL, "rdcnn_batch_set_adjoint_kernel: depth %d not in {1,2,4,8}", depth);
     if (cols_per_lane != 1 && cols_per_lane != 2)
@@ -759,9 +761,12 @@ int rdcnn_batch_adjoint(rdcnn_batch_t b, const float *traj, long long S, float *
     if (!adj || !adj_tmp || !dtheta || (S > 0 && !traj))
         return bfail(RDCNN_EINVAL, "rdcnn_batch_adjoint: NULL buffer");
     if (adj == adj_tmp) return bfail(RDCNN_EINVAL, "rdcnn_batch_adjoint: adj and adj_tmp alias");
-    if (state_depth_cap(b, b->adj_depth) < b->adj_depth)
-        return bfail(RDCNN_EINVAL, "rdcnn_batch_adjoint: packed state too large for depth %d",
-                     b->adj_depth);
+    // deepest pass whose states fit one buffer resource (the tile list is cut
+    // for adj_depth; shallower passes reuse it)
+    int kmax = b->adj_depth;
+    const int cap = state_depth_cap(b, kmax);
+    if (cap < 1) return bfail(RDCNN_EINVAL, "rdcnn_batch_adjoint: packed state too large");
+    while (kmax > cap) kmax >>= 1;
     if (!b->adj_partial) {
         const int rc = setup_adj(b);
         if (rc != RDCNN_OK) return rc;
@@ -772,7 +777,7 @@ int rdcnn_batch_adjoint(rdcnn_batch_t b, const float *traj, long long S, float *
     float *src = adj, *dst = adj_tmp;
     long long top = S - 1;  // state the next reverse step steps back over
     while (e == hipSuccess && top >= 0 && ntiles > 0) {
-        int k = b->adj_depth;
+        int k = kmax;
         while (k > 1 && k > top + 1) k >>= 1;
         e = rd::launch_batch_adjoint(b->adj_table.dev, b->insts_dev, ntiles, src, dst,
                                      traj + (top - k + 1) * b->total, (unsigned)(4 * b->total),
