@@ -80,7 +80,17 @@ rd::Gene to_gene(const rdcnn_params_t *p)
 void auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows, bool record)
 {
     *seg_rows = 0;
-    if (h->R >= 2048 && h->C >= 2048 && !record) {
+    if (record) {
+        // Recording is bound by its stores; two columns per lane and segments
+        // for ~2560 wavefronts led a sweep on 1024^2 (7 % over one column).
+        *cpl = 2;
+        *depth = 8;
+        const long long nstrips = (h->C + 111) / 112;
+        long long want = 2560 / nstrips;
+        if (want < 1) want = 1;
+        long long seg = (h->R + want - 1) / want;
+        *seg_rows = (int)(seg < 4 ? 4 : seg);
+    } else if (h->R >= 2048 && h->C >= 2048) {
         *cpl = 4;
         *depth = 8;
     } else {
@@ -173,11 +183,21 @@ int run_steps(rdcnn_sim *h, long long n, float *rec)
 // Gradients that need the lam-weighted sums: dt (bit 0), c (bit 4), k3 (bit 5).
 constexpr unsigned kLamSumGrads = (1u << 0) | (1u << 4) | (1u << 5);
 
-void adj_auto_config(const rdcnn_sim *, int *cpl, int *depth, int *seg_rows)
+// Adjoint pass shape: one column per lane, four reverse steps, and segments
+// short enough for about 4608 wavefronts (4.5 per SIMD).  The adjoint waits on
+// memory more than the forward, so it gains from more resident wavefronts
+// despite the extra halo rows (a sweep on 1024^2: 8 % over two columns per lane
+// and ~2048 wavefronts).
+void adj_auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows)
 {
-    *cpl = 2;
+    *cpl = 1;
     *depth = 4;
-    *seg_rows = 0;
+    const long long nstrips = (h->C + (64 - 2 * 4) - 1) / (64 - 2 * 4);
+    long long want = 4608 / nstrips;
+    if (want < 1) want = 1;
+    long long seg = (h->R + want - 1) / want;
+    if (seg < 4) seg = 4;  // as the forward's automatic segments
+    *seg_rows = (int)seg;
 }
 
 int check_grid(const char *who, int rows, int cols, int bc, const float *buf0, const float *buf1)
