@@ -535,7 +535,7 @@ int state_depth_cap(const rdcnn_batch *b, int want)
 // Enqueue the launches of T steps; cur flips once per streamed launch.  The
 // in-LDS instances go first, in one launch, and write their final state to the
 // buffer that will be current after the T steps.
-int enqueue_steps(rdcnn_batch *b, long long T, int cpl, int depth, int seg)
+int enqueue_steps(rdcnn_batch *b, long long T, int cpl, int depth)
 {
     if (b->lds_count > 0 && T > 0) {
         const long long passes = (T + depth - 1) / depth;
@@ -873,7 +873,7 @@ int rdcnn_batch_step(rdcnn_batch_t b, long long T)
     if (rc == RDCNN_OK && T % depth) rc = table_for(b, cpl, (int)(T % depth), seg, &t);
     if (rc != RDCNN_OK) return rc;
     const long long passes = (T + depth - 1) / depth;
-    if (!b->use_graph) return enqueue_steps(b, T, cpl, depth, seg);
+    if (!b->use_graph) return enqueue_steps(b, T, cpl, depth);
     if (!b->stream) return bfail(RDCNN_EINVAL, "batch: graph capture needs a non-default stream");
     if (!(b->graph && b->graph_T == T && b->graph_cur == b->cur && b->graph_cpl == cpl &&
           b->graph_depth == depth && b->graph_seg == seg)) {
@@ -881,7 +881,7 @@ int rdcnn_batch_step(rdcnn_batch_t b, long long T)
         const int cur0 = b->cur;
         hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed);
         if (e != hipSuccess) return bfail(RDCNN_EHIP, "batch: begin capture: %s", hipGetErrorString(e));
-        rc = enqueue_steps(b, T, cpl, depth, seg);
+        rc = enqueue_steps(b, T, cpl, depth);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->stream, &g);
         b->cur = cur0;
