@@ -121,7 +121,8 @@ def bench_fwd_bwd(stream):
     tfb8 = min(_timed(lambda: fwd_bwd(None), stream) for _ in range(3))
     cells = N * N * T
     return {"workload": "1024x1024 zero-flux, T=2000, MSE to stripe target, grads wrt x, Du, Dv "
-                        "and eps; whole trajectory recorded in HBM",
+                        "and eps; states of even times recorded in HBM, odd ones rebuilt in the "
+                        "reverse passes",
             "fwd_gcells": cells / tf / 1e9, "fwd_bwd_gcells": cells / tfb / 1e9,
             "fwd_ms": tf * 1e3, "fwd_bwd_ms": tfb * 1e3, "ratio_fwd_bwd_to_fwd": tfb / tf,
             "fwd_bwd_all8_ms": tfb8 * 1e3, "ratio_all8_to_fwd": tfb8 / tf}
@@ -307,8 +308,8 @@ def bench_edge_fit(stream, n_img=64, iters=4):
     random rectangles of levels U[-1,1] plus N(0, 0.05^2) noise), x = image,
     T = 50, zero-flux; Du, Dv and epsilon (shared by all images) fitted by Adam
     to the normalized Sobel magnitude of the clean images.  Each iteration is
-    one batched forward+backward over all 64 images (simulate_batch: recording
-    batch kernel, batched adjoint kernel).  Reports the loss curve, the fwd+bwd
+    one batched forward+backward over all 64 images (simulate_batch: even-time
+    recording batch kernel, batched paired reverse passes).  Reports the loss curve, the fwd+bwd
     rate, and for comparison one iteration run image by image over four
     streams with the single-grid path."""
     import torch

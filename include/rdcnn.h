@@ -197,6 +197,30 @@ int rdcnn_adjoint(rdcnn_t h, const float *states_dev, long long S, float *adj_de
                   float *adj_tmp_dev, double *dtheta_dev);
 
 /*
+ * rdcnn_step_record_even -- like rdcnn_step_record, but keeps only the states
+ * of even times counted from the handle's current time: s_{t+2i} goes to
+ * states_dev[i] for 2i < T, i.e. (T+1)/2 states of 2*rows*cols floats each
+ * (half the memory and half the writes).  Passes run 8 steps (or the even
+ * depth set with rdcnn_set_kernel; at most 8, one or two columns per lane).
+ * These are the states rdcnn_adjoint_even reads.  Asynchronous.
+ * Errors: RDCNN_EINVAL, RDCNN_EHIP.
+ */
+int rdcnn_step_record_even(rdcnn_t h, long long T, float *states_dev);
+
+/*
+ * rdcnn_adjoint_even -- rdcnn_adjoint from an even-time trajectory: the same
+ * reverse pass through S steps of Eq. (1)-(3) (same arguments, results and
+ * errors), with states_dev as written by rdcnn_step_record_even
+ * (states_dev[i] = s_{t0+2i}, (S+1)/2 states).  Each reverse pass rebuilds
+ * the odd-time states it needs from the even ones with the forward cell
+ * update, bit-identical to the forward pass, so (dJ/du, dJ/dv) equals
+ * rdcnn_adjoint's bit for bit.  Uses rdcnn_set_adjoint_kernel's settings with
+ * an even depth of 2..8 and at most two columns per lane.
+ */
+int rdcnn_adjoint_even(rdcnn_t h, const float *states_dev, long long S, float *adj_dev,
+                       float *adj_tmp_dev, double *dtheta_dev);
+
+/*
  * rdcnn_set_adjoint_kernel -- pass settings for rdcnn_adjoint: `depth` reverse
  * steps per HBM pass, cols_per_lane 1 or 2 (depth 1..8) or 4 (depth 1..6), seg_rows
  * output rows per wavefront (0 = automatic).  depth = cols_per_lane = 0 restores
@@ -331,6 +355,26 @@ int rdcnn_batch_set_adjoint_kernel(rdcnn_batch_t b, int depth, int cols_per_lane
  */
 int rdcnn_batch_adjoint(rdcnn_batch_t b, const float *traj, long long S, float *adj,
                         float *adj_tmp, unsigned mask, double *dtheta);
+
+/*
+ * rdcnn_batch_step_record_even -- rdcnn_batch_step_record keeping only the
+ * states of even times: packed state 2i goes to traj + i * buf_floats for
+ * 2i < T ((T+1)/2 states; half the memory and writes).  Passes take an even
+ * depth (at most 8).  The trajectory rdcnn_batch_adjoint_even reads.
+ * Errors: as rdcnn_batch_step_record.
+ */
+int rdcnn_batch_step_record_even(rdcnn_batch_t b, long long T, float *traj);
+
+/*
+ * rdcnn_batch_adjoint_even -- rdcnn_batch_adjoint from an even-time trajectory
+ * (rdcnn_batch_step_record_even; (S+1)/2 packed states).  Each paired reverse
+ * pass rebuilds the odd-time states from the even ones with the forward cell
+ * update, bit-identical to the forward pass, so dJ/ds equals
+ * rdcnn_batch_adjoint's bit for bit.  Same arguments, outputs and errors;
+ * also RDCNN_EINVAL when the adjoint depth is 1 (paired passes take 2 or more).
+ */
+int rdcnn_batch_adjoint_even(rdcnn_batch_t b, const float *traj, long long S, float *adj,
+                             float *adj_tmp, unsigned mask, double *dtheta);
 
 /*
  * rdcnn_batch_stats -- per-instance statistics of the current state for a

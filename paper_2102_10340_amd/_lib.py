@@ -54,6 +54,8 @@ _SIGS = {
     "rdcnn_destroy": [_P],
     "rdcnn_step_record": [_P, _LL, _P],
     "rdcnn_adjoint": [_P, _P, _LL, _P, _P, _P],
+    "rdcnn_step_record_even": [_P, _LL, _P],
+    "rdcnn_adjoint_even": [_P, _P, _LL, _P, _P, _P],
     "rdcnn_set_adjoint_kernel": [_P, _I, _I, _I],
     "rdcnn_init_backward": [_P, _LL, _F, _P, _P],
     "rdcnn_set_grad_mask": [_P, ctypes.c_uint],
@@ -69,6 +71,8 @@ _SIGS = {
     "rdcnn_batch_step_record": [_P, _LL, _P],
     "rdcnn_batch_set_adjoint_kernel": [_P, _I, _I, _I],
     "rdcnn_batch_adjoint": [_P, _P, _LL, _P, _P, ctypes.c_uint, _P],
+    "rdcnn_batch_step_record_even": [_P, _LL, _P],
+    "rdcnn_batch_adjoint_even": [_P, _P, _LL, _P, _P, ctypes.c_uint, _P],
     "rdcnn_batch_destroy": [_P],
 }
 for _name, _args in _SIGS.items():

@@ -1,15 +1,18 @@
 """Differentiable RD-CNN runs: torch.autograd.Function wrappers around the
 library's forward, state-recording and adjoint kernels.
 
-Two schedules, chosen by S:
-* S = -1, whole trajectory: the forward records all T states (8 bytes per cell
-  and step) and the backward runs the adjoint kernel straight through them, with
-  no recomputation.  An MI355X has 288 GB of HBM, so this is the default whenever
-  the trajectory fits a quarter of the free device memory (16 GiB for
-  1024x1024 x 2000 steps).
+Both schedules keep only the states of even times (rdcnn_step_record_even,
+4 bytes per cell and step); the paired reverse passes (rdcnn_adjoint_even)
+rebuild each odd state from the even one before it with the forward cell
+update, bit-identical to the forward pass, so the gradients equal those of a
+fully recorded trajectory.  The schedule is chosen by S:
+* S = -1, whole trajectory: the forward records the even states and the
+  backward runs the adjoint straight through them.  An MI355X has 288 GB of
+  HBM, so this is the default whenever the trajectory fits a quarter of the
+  free device memory (8 GiB for 1024x1024 x 2000 steps).
 * S > 0, checkpoint-and-recompute: the forward keeps one checkpoint every S
   steps; the backward walks the segments from last to first, restores a
-  checkpoint, re-runs the segment while recording its S states and runs the
+  checkpoint, re-runs the segment while recording its even states and runs the
   adjoint through them.  With S near sqrt(T) memory is O(sqrt(T)) states; the
   default S is ceil(sqrt(T)) capped so that one segment's states stay within
   half of the 256 MB last-level cache, where the adjoint reads them right after
@@ -33,9 +36,9 @@ LLC_BYTES = 256 << 20
 
 
 def default_segment(T: int, rows: int, cols: int) -> int:
-    """ceil(sqrt(T)), capped so that a segment of states fits half the last-level cache."""
+    """ceil(sqrt(T)), capped so that a segment's even states fit half the last-level cache."""
     s = max(1, math.ceil(math.sqrt(max(T, 1))))
-    cap = max(1, (LLC_BYTES // 2) // (8 * rows * cols))
+    cap = max(1, 2 * ((LLC_BYTES // 2) // (8 * rows * cols)))
     return max(1, min(s, cap, T if T > 0 else 1))
 
 
@@ -43,7 +46,7 @@ def choose_schedule(T: int, rows: int, cols: int, S: int, device) -> int:
     """-1 (record the whole trajectory) or a checkpoint spacing > 0."""
     if S != 0:
         return S
-    need = 8 * rows * cols * max(T, 1)
+    need = 8 * rows * cols * max((T + 1) // 2, 1)
     free, _ = torch.cuda.mem_get_info(device)
     if need <= free // 4:
         return -1
@@ -68,9 +71,10 @@ def _gene(theta: torch.Tensor):
 
 
 def _forward(sim: Simulation, T: int, S: int, dev):
-    if S < 0:  # whole trajectory
-        states = torch.empty((max(T, 1), 2, sim.rows, sim.cols), dtype=torch.float32, device=dev)
-        sim.step_record(T, states)
+    if S < 0:  # whole trajectory, even times
+        states = torch.empty((max((T + 1) // 2, 1), 2, sim.rows, sim.cols), dtype=torch.float32,
+                             device=dev)
+        sim.step_record_even(T, states)
         u, v = sim.read()
         return u, v, states, 0
     nseg = -(-T // S) if T > 0 else 0
@@ -93,15 +97,15 @@ def _backward(sim: Simulation, ckpt, nseg: int, T: int, S: int, gu, gv, dev, ker
     if kernel is not None:
         sim.set_adjoint_kernel(*kernel)
     sim.set_grad_mask(mask)
-    if S < 0:  # ckpt holds the whole recorded trajectory
-        sim.adjoint(ckpt, T, adj, tmp, dtheta)
+    if S < 0:  # ckpt holds the whole even-time trajectory
+        sim.adjoint_even(ckpt, T, adj, tmp, dtheta)
         return adj, dtheta
-    seg = torch.empty((min(S, max(T, 1)), 2, R, C), dtype=torch.float32, device=dev)
+    seg = torch.empty(((min(S, max(T, 1)) + 1) // 2, 2, R, C), dtype=torch.float32, device=dev)
     for k in range(nseg - 1, -1, -1):
         L = min(S, T - k * S)
         sim.write_state_packed(ckpt[k])
-        sim.step_record(L, seg)
-        sim.adjoint(seg, L, adj, tmp, dtheta)
+        sim.step_record_even(L, seg)
+        sim.adjoint_even(seg, L, adj, tmp, dtheta)
     return adj, dtheta
 
 
@@ -177,9 +181,9 @@ def simulate_state(u0, v0, theta, T, bc="zeroflux", S=0, grads=None):
 class RDCNNBatchFunction(torch.autograd.Function):
     """(theta, x_1 .. x_n) -> (u_T,1, v_T,1, ..., u_T,n, v_T,n) of a batch,
     u_0 = v_0 = ka x_i.  theta is [8] (shared by every instance) or [n, 8] (one
-    gene per instance).  The forward records the whole packed trajectory when it
-    fits a quarter of the free memory (else a checkpoint every S steps); the
-    backward runs the batched adjoint kernel.  Separate outputs per instance
+    gene per instance).  The forward records the packed states of even times
+    when they fit a quarter of the free memory (else a checkpoint every S
+    steps); the backward runs the batched paired reverse passes.  Separate outputs per instance
     keep autograd from forming a full-size gradient per instance."""
 
     @staticmethod
@@ -199,10 +203,11 @@ class RDCNNBatchFunction(torch.autograd.Function):
         T = int(T)
         if S == 0:
             free, _ = torch.cuda.mem_get_info(dev)
-            S = -1 if 4 * b.total * max(T, 1) <= free // 4 else max(1, math.ceil(math.sqrt(T)))
+            S = -1 if 4 * b.total * max((T + 1) // 2, 1) <= free // 4 else \
+                max(1, math.ceil(math.sqrt(T)))
         if S < 0:
-            store = torch.empty((max(T, 1), b.total), dtype=torch.float32, device=dev)
-            b.step_record(T, store)
+            store = torch.empty((max((T + 1) // 2, 1), b.total), dtype=torch.float32, device=dev)
+            b.step_record_even(T, store)
             nseg = 0
         else:
             nseg = -(-T // S) if T > 0 else 0
@@ -231,14 +236,15 @@ class RDCNNBatchFunction(torch.autograd.Function):
         tmp = torch.empty_like(adj)
         dtheta = torch.zeros((len(b), 8), dtype=torch.float64, device=adj.device)
         if S < 0:
-            b.adjoint(ctx.store, T, adj, tmp, ctx.mask, dtheta)
+            b.adjoint_even(ctx.store, T, adj, tmp, ctx.mask, dtheta)
         else:
-            seg = torch.empty((min(S, max(T, 1)), b.total), dtype=torch.float32, device=adj.device)
+            seg = torch.empty(((min(S, max(T, 1)) + 1) // 2, b.total), dtype=torch.float32,
+                              device=adj.device)
             for k in range(ctx.nseg - 1, -1, -1):
                 L = min(S, T - k * S)
                 b.write_state(ctx.store[k])
-                b.step_record(L, seg)
-                b.adjoint(seg, L, adj, tmp, ctx.mask, dtheta)
+                b.step_record_even(L, seg)
+                b.adjoint_even(seg, L, adj, tmp, ctx.mask, dtheta)
         gxs = [init_backward(b.view(adj, i), ctx.ka) for i in range(len(b))]
         b.close()
         dt, dd, dim = ctx.theta_meta

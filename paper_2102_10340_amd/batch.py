@@ -100,13 +100,25 @@ class Batch:
         self._keep = packed
         check(lib.rdcnn_batch_write_state(self._h, packed.data_ptr()))
 
+    def _check_traj(self, traj, n):
+        if (traj.dtype != torch.float32 or not traj.is_contiguous() or traj.dim() != 2
+                or traj.shape[0] < n or traj.shape[1] != self.total):
+            raise ValueError("traj must be contiguous float32 [>= %d, total]" % n)
+
     def step_record(self, T: int, traj: torch.Tensor) -> "Batch":
         """Advance T steps, writing the packed state each step starts from into
         traj[q] (float32 [>= T, total], contiguous)."""
-        if T > 0 and (traj.dtype != torch.float32 or not traj.is_contiguous() or traj.dim() != 2
-                      or traj.shape[0] < T or traj.shape[1] != self.total):
-            raise ValueError("traj must be contiguous float32 [>= T, total]")
+        if T > 0:
+            self._check_traj(traj, T)
         check(lib.rdcnn_batch_step_record(self._h, int(T), traj.data_ptr() if T > 0 else None))
+        return self
+
+    def step_record_even(self, T: int, traj: torch.Tensor) -> "Batch":
+        """Advance T steps keeping the packed states of even times: state 2i in
+        traj[i] (float32 [>= (T+1)//2, total]); what adjoint_even reads."""
+        if T > 0:
+            self._check_traj(traj, (T + 1) // 2)
+        check(lib.rdcnn_batch_step_record_even(self._h, int(T), traj.data_ptr() if T > 0 else None))
         return self
 
     def set_adjoint_kernel(self, depth: int = 0, cols_per_lane: int = 0, seg_rows: int = 0) -> None:
@@ -118,16 +130,30 @@ class Batch:
         """Reverse pass through the S steps recorded in traj[0..S-1] for every
         instance: adj (packed) goes from dJ/ds after to dJ/ds before; per-instance
         parameter gradients are added to dtheta (float64 [n, 8])."""
+        self._check_adjoint(adj, adj_tmp, dtheta)
+        if S > 0:
+            self._check_traj(traj, S)
+        check(lib.rdcnn_batch_adjoint(self._h, traj.data_ptr() if S > 0 else None, int(S),
+                                      adj.data_ptr(), adj_tmp.data_ptr(), int(mask) & 0xFF,
+                                      dtheta.data_ptr()))
+
+    def adjoint_even(self, traj: torch.Tensor, S: int, adj: torch.Tensor, adj_tmp: torch.Tensor,
+                     mask: int, dtheta: torch.Tensor) -> None:
+        """adjoint() from an even-time trajectory (step_record_even); the odd
+        states are rebuilt inside the reverse passes, with the same results."""
+        self._check_adjoint(adj, adj_tmp, dtheta)
+        if S > 0:
+            self._check_traj(traj, (S + 1) // 2)
+        check(lib.rdcnn_batch_adjoint_even(self._h, traj.data_ptr() if S > 0 else None, int(S),
+                                           adj.data_ptr(), adj_tmp.data_ptr(), int(mask) & 0xFF,
+                                           dtheta.data_ptr()))
+
+    def _check_adjoint(self, adj, adj_tmp, dtheta):
         for t in (adj, adj_tmp):
             if t.dtype != torch.float32 or t.numel() < self.total or not t.is_contiguous():
                 raise ValueError("adj buffers must be contiguous float32 of the batch's size")
         if dtheta.dtype != torch.float64 or tuple(dtheta.shape) != (len(self), 8) or not dtheta.is_contiguous():
             raise ValueError("dtheta must be contiguous float64 [n, 8]")
-        if S > 0 and (traj.dim() != 2 or traj.shape[0] < S or traj.shape[1] != self.total):
-            raise ValueError("traj must be [>= S, total]")
-        check(lib.rdcnn_batch_adjoint(self._h, traj.data_ptr() if S > 0 else None, int(S),
-                                      adj.data_ptr(), adj_tmp.data_ptr(), int(mask) & 0xFF,
-                                      dtheta.data_ptr()))
 
     def view(self, packed: torch.Tensor, i: int) -> torch.Tensor:
         """View [2, R, C] of instance i in a packed tensor of this batch's layout."""

@@ -77,10 +77,22 @@ rd::Gene to_gene(const rdcnn_params_t *p)
 // Default pass settings for a grid when the caller has not forced any (from
 // sweeps on MI355X: wide strips and deep passes pay off only on large grids;
 // smaller grids are latency bound and want more, narrower wavefronts).
-void auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows, bool record)
+void auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows, bool record,
+                 bool record_even = false)
 {
     *seg_rows = 0;
-    if (record) {
+    if (record && record_even) {
+        // Even-state recording writes half as much; one column per lane and
+        // segments for ~2816 wavefronts led a sweep on 1024^2 (10 % over the
+        // full recording's shape).
+        *cpl = 1;
+        *depth = 8;
+        const long long nstrips = (h->C + 47) / 48;
+        long long want = 2816 / nstrips;
+        if (want < 1) want = 1;
+        long long seg = (h->R + want - 1) / want;
+        *seg_rows = (int)(seg < 4 ? 4 : seg);
+    } else if (record) {
         // Recording is bound by its stores; two columns per lane and segments
         // for ~2560 wavefronts led a sweep on 1024^2 (7 % over one column).
         *cpl = 2;
@@ -131,8 +143,9 @@ int run_model_steps(rdcnn_sim *h, long long n)
 }
 
 // Run n steps from buf[cur]; flips cur once per pass.  If rec is not null the
-// state each step starts from is also written to rec[0..n-1] (2*R*C floats each).
-int run_steps(rdcnn_sim *h, long long n, float *rec)
+// state each step starts from is also written to rec[0..n-1] (2*R*C floats
+// each); with rec_even only the states of even times, s_{2i} to rec[i].
+int run_steps(rdcnn_sim *h, long long n, float *rec, bool rec_even = false)
 {
     if (h->model != rd::MODEL_FHN) {
         if (rec) return fail(RDCNN_EINVAL, "rdcnn_step_record: FitzHugh-Nagumo grids only");
@@ -142,14 +155,23 @@ int run_steps(rdcnn_sim *h, long long n, float *rec)
     int kind = h->kind, cpl = h->cpl, depth = h->depth, seg = h->seg_rows;
     if (kind == 0) {
         kind = 2;
-        auto_config(h, &cpl, &depth, &seg, rec != nullptr);
+        auto_config(h, &cpl, &depth, &seg, rec != nullptr, rec_even);
     }
     if (rec && kind == 2) {
         // A pass's recorded states are addressed through one 4 GiB buffer resource.
         const long long cap = ((1LL << 32) - 1) / (8LL * h->R * h->C);
         if (cap < 1)
             return fail(RDCNN_EINVAL, "rdcnn_step_record: grid too large to record");
-        if (depth > cap) depth = (int)cap;
+        if (rec_even) {
+            // Even-state recording: every pass but the last starts at an even
+            // time, so passes of an even depth (<= 8; one or two columns per lane).
+            if (cpl > 2) cpl = 2;
+            if (depth > 8) depth = 8;
+            if (depth > 2 * cap) depth = (int)(2 * cap);
+            if (depth > 1) depth &= ~1;
+        } else if (depth > cap) {
+            depth = (int)cap;
+        }
     }
     while (n > 0) {
         hipError_t e;
@@ -158,9 +180,10 @@ int run_steps(rdcnn_sim *h, long long n, float *rec)
         long long done;
         if (kind == 1) {
             e = hipSuccess;
-            if (rec)
-                e = hipMemcpyAsync(rec + q * 2LL * h->R * h->C, in, sizeof(float) * 2 * h->R * h->C,
-                                   hipMemcpyDeviceToDevice, h->stream);
+            if (rec && (!rec_even || q % 2 == 0))
+                e = hipMemcpyAsync(rec + (rec_even ? q / 2 : q) * 2LL * h->R * h->C, in,
+                                   sizeof(float) * 2 * h->R * h->C, hipMemcpyDeviceToDevice,
+                                   h->stream);
             if (e == hipSuccess) e = rd::launch_naive(in, out, h->R, h->C, h->bc, h->g, h->stream);
             done = 1;
         } else {
@@ -169,7 +192,11 @@ int run_steps(rdcnn_sim *h, long long n, float *rec)
             if (!rd::stream_geometry(h->R, h->C, cpl, k, seg, &geom))
                 return fail(RDCNN_EINVAL, "rdcnn_step: cannot tile %dx%d with cpl=%d depth=%d",
                             h->R, h->C, cpl, k);
-            e = rd::launch_stream(in, out, h->R, h->C, h->bc, h->g, geom, h->stream, rec, q);
+            if (rec && rec_even && q % 2 == 1)  // depth-1 passes: odd times are not kept
+                e = rd::launch_stream(in, out, h->R, h->C, h->bc, h->g, geom, h->stream);
+            else
+                e = rd::launch_stream(in, out, h->R, h->C, h->bc, h->g, geom, h->stream, rec,
+                                      rec_even ? q / 2 : q, rec_even);
             done = k;
         }
         if (e != hipSuccess) return hip_fail(e, "rdcnn_step: kernel launch");
@@ -327,6 +354,15 @@ int rdcnn_step_record(rdcnn_t h, long long T, float *states_dev)
     return run_steps(h, T, states_dev);
 }
 
+int rdcnn_step_record_even(rdcnn_t h, long long T, float *states_dev)
+{
+    if (!h) return fail(RDCNN_EINVAL, "rdcnn_step_record_even: NULL handle");
+    if (T < 0) return fail(RDCNN_EINVAL, "rdcnn_step_record_even: T = %lld < 0", T);
+    if (T > 0 && !states_dev)
+        return fail(RDCNN_EINVAL, "rdcnn_step_record_even: NULL states buffer");
+    return run_steps(h, T, states_dev, true);
+}
+
 int rdcnn_set_adjoint_kernel(rdcnn_t h, int depth, int cols_per_lane, int seg_rows)
 {
     if (!h) return fail(RDCNN_EINVAL, "rdcnn_set_adjoint_kernel: NULL handle");
@@ -409,6 +445,93 @@ int rdcnn_adjoint(rdcnn_t h, const float *states_dev, long long S, float *adj_de
     }
     e = rd::launch_adjoint_finish(h->partial, (int)need, h->g, h->grad_mask, dtheta_dev, h->stream);
     if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint: finish");
+    return RDCNN_OK;
+}
+
+int rdcnn_adjoint_even(rdcnn_t h, const float *states_dev, long long S, float *adj_dev,
+                       float *adj_tmp_dev, double *dtheta_dev)
+{
+    if (!h) return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: NULL handle");
+    if (h->model != rd::MODEL_FHN)
+        return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: FitzHugh-Nagumo grids only");
+    if (S < 0) return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: S = %lld < 0", S);
+    if (!adj_dev || !adj_tmp_dev || !dtheta_dev || (S > 0 && !states_dev))
+        return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: NULL argument");
+    if (adj_dev == adj_tmp_dev) return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: adj buffers alias");
+    if (S == 0) return RDCNN_OK;
+    int cpl = h->adj_cpl, depth = h->adj_depth, seg = h->adj_seg_rows;
+    if (depth == 0) adj_auto_config(h, &cpl, &depth, &seg);
+    // Paired passes: an even depth of 2..8, one or two columns per lane.
+    if (cpl > 2) cpl = 2;
+    if (depth > 8) depth = 8;
+    if (depth < 2) depth = 2;
+    depth &= ~1;
+    {
+        // A pass reads its depth/2 even states through one 4 GiB buffer resource.
+        const long long cap = ((1LL << 32) - 1) / (8LL * h->R * h->C);
+        if (cap < 1) return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: grid too large");
+        if (depth > 2 * cap) depth = (int)(2 * cap);
+    }
+    // An odd S starts with one plain reverse step (state s_{S-1} is even);
+    // then paired passes of `depth` steps and one shorter even remainder.
+    const long long even = S & ~1LL;
+    const int klast = even == 0 ? 0 : (int)(even % depth == 0 ? depth : even % depth);
+    long long need = 0;
+    for (int k : {(S & 1) ? 1 : 0, (int)(even < depth ? even : depth), klast}) {
+        if (k == 0) continue;
+        rd::StreamGeom gk;
+        if (!rd::stream_geometry(h->R, h->C, cpl, k, seg, &gk))
+            return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: cannot tile %dx%d", h->R, h->C);
+        if (gk.ntiles > need) need = gk.ntiles;
+    }
+    if (need > h->partial_cap) {
+        if (h->partial) (void)hipFree(h->partial);
+        h->partial = nullptr;
+        h->partial_cap = 0;
+        hipError_t e = hipMalloc((void **)&h->partial, sizeof(double) * rd::kAdjSums * need);
+        if (e != hipSuccess) {
+            h->partial = nullptr;
+            return fail(RDCNN_ENOMEM, "rdcnn_adjoint_even: partial buffer: %s",
+                        hipGetErrorString(e));
+        }
+        h->partial_cap = need;
+    }
+    hipError_t e = rd::launch_zero(h->partial, rd::kAdjSums * need, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint_even: zero");
+    const bool lam_sums = (h->grad_mask & kLamSumGrads) != 0;
+    float *cur = adj_dev, *other = adj_tmp_dev;
+    auto flip = [&]() {
+        float *tmp = cur;
+        cur = other;
+        other = tmp;
+    };
+    if (S & 1) {
+        rd::StreamGeom geom;
+        if (!rd::stream_geometry(h->R, h->C, cpl, 1, seg, &geom))
+            return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: cannot tile %dx%d", h->R, h->C);
+        e = rd::launch_adjoint(cur, other, states_dev, (S - 1) / 2, h->R, h->C, h->bc, h->g, geom,
+                               h->partial, lam_sums, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint_even: kernel launch");
+        flip();
+    }
+    for (long long t_top = even; t_top > 0;) {
+        const int k = (int)(t_top < depth ? t_top : depth);
+        rd::StreamGeom geom;
+        if (!rd::stream_geometry(h->R, h->C, cpl, k, seg, &geom))
+            return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: cannot tile %dx%d", h->R, h->C);
+        e = rd::launch_adjoint_pair(cur, other, states_dev, t_top, h->R, h->C, h->bc, h->g, geom,
+                                    h->partial, lam_sums, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint_even: kernel launch");
+        flip();
+        t_top -= k;
+    }
+    if (cur != adj_dev) {
+        e = hipMemcpyAsync(adj_dev, cur, sizeof(float) * 2 * (size_t)h->R * h->C,
+                           hipMemcpyDeviceToDevice, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint_even: copy back");
+    }
+    e = rd::launch_adjoint_finish(h->partial, (int)need, h->g, h->grad_mask, dtheta_dev, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint_even: finish");
     return RDCNN_OK;
 }
 

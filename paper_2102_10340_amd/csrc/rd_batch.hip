@@ -33,7 +33,9 @@ struct BatchArgs {
     unsigned rec_stride;  // bytes between packed states
 };
 
-template <int CPL, int K, bool REC>
+// REC: 0 plain steps; 1 record every level; 2 record the even levels (passes
+// start at even times).
+template <int CPL, int K, int REC>
 __global__ __launch_bounds__(64) void batch_step_kernel(BatchArgs B)
 {
     const int id = blockIdx.x;
@@ -196,7 +198,7 @@ namespace {
 
 using BatchFn = void (*)(BatchArgs);
 
-template <int CPL, bool REC, int... Ks>
+template <int CPL, int REC, int... Ks>
 constexpr BatchFn pick(int k, std::integer_sequence<int, Ks...>)
 {
     BatchFn f = nullptr;
@@ -208,20 +210,25 @@ constexpr BatchFn pick(int k, std::integer_sequence<int, Ks...>)
 
 hipError_t launch_batch(const BatchTile *tiles, const BatchInst *insts, int ntiles,
                         const float *in, float *out, int bc, int cpl, int depth, hipStream_t s,
-                        float *rec, unsigned rec_stride)
+                        float *rec, unsigned rec_stride, bool rec_even)
 {
     BatchFn f = nullptr;
-    if (rec) {  // recording passes: cpl 1 or 2, depth <= 8
+    if (rec && rec_even) {  // recording passes: cpl 1 or 2, depth <= 8
         if (cpl == 2)
-            f = pick<2, true>(depth, std::make_integer_sequence<int, 8>{});
+            f = pick<2, 2>(depth, std::make_integer_sequence<int, 8>{});
         else if (cpl == 1)
-            f = pick<1, true>(depth, std::make_integer_sequence<int, 8>{});
+            f = pick<1, 2>(depth, std::make_integer_sequence<int, 8>{});
+    } else if (rec) {
+        if (cpl == 2)
+            f = pick<2, 1>(depth, std::make_integer_sequence<int, 8>{});
+        else if (cpl == 1)
+            f = pick<1, 1>(depth, std::make_integer_sequence<int, 8>{});
     } else if (cpl == 4) {
-        f = pick<4, false>(depth, std::make_integer_sequence<int, kMaxDepthCpl4>{});
+        f = pick<4, 0>(depth, std::make_integer_sequence<int, kMaxDepthCpl4>{});
     } else if (cpl == 2) {
-        f = pick<2, false>(depth, std::make_integer_sequence<int, kMaxDepthCpl2>{});
+        f = pick<2, 0>(depth, std::make_integer_sequence<int, kMaxDepthCpl2>{});
     } else if (cpl == 1) {
-        f = pick<1, false>(depth, std::make_integer_sequence<int, kMaxDepthCpl1>{});
+        f = pick<1, 0>(depth, std::make_integer_sequence<int, kMaxDepthCpl1>{});
     }
     if (!f || ntiles < 1) return hipErrorInvalidValue;
     BatchArgs a;
@@ -696,20 +703,31 @@ int rdcnn_batch_write_state(rdcnn_batch_t b, const float *packed)
     return RDCNN_OK;
 }
 
-int rdcnn_batch_step_record(rdcnn_batch_t b, long long T, float *traj)
+namespace {
+
+// Recording passes of T steps; with even, only the states of even times
+// (s_{2i} to traj[i]).
+int batch_record(rdcnn_batch *b, long long T, float *traj, bool even, const char *who)
 {
-    if (!b) return bfail(RDCNN_EINVAL, "rdcnn_batch_step_record: NULL handle");
-    if (T < 0) return bfail(RDCNN_EINVAL, "rdcnn_batch_step_record: T = %lld < 0", T);
+    if (!b) return bfail(RDCNN_EINVAL, "%s: NULL handle", who);
+    if (T < 0) return bfail(RDCNN_EINVAL, "%s: T = %lld < 0", who, T);
     if (T == 0) return RDCNN_OK;
-    if (!traj) return bfail(RDCNN_EINVAL, "rdcnn_batch_step_record: NULL trajectory");
+    if (!traj) return bfail(RDCNN_EINVAL, "%s: NULL trajectory", who);
     int cpl, depth, seg;
     batch_config(b, &cpl, &depth, &seg);
     if (cpl > 2) cpl = 2;  // recording passes exist for 1 or 2 columns per lane
     if (depth > 8) depth = 8;
     if (!b->seg_rows) seg = 64;  // recording is write-bound; shorter tiles led a sweep
-    depth = state_depth_cap(b, depth);
-    if (depth < 1)
-        return bfail(RDCNN_EINVAL, "rdcnn_batch_step_record: packed state too large to record");
+    if (even) {
+        // a pass spans depth/2 recorded states; every pass but the last starts
+        // at an even time, so the depth is even
+        const int cap = state_depth_cap(b, 4);
+        if (depth > 2 * cap) depth = 2 * cap;
+        if (depth > 1) depth &= ~1;
+    } else {
+        depth = state_depth_cap(b, depth);
+    }
+    if (depth < 1) return bfail(RDCNN_EINVAL, "%s: packed state too large to record", who);
     if (cpl != b->rec_cpl) {
         for (TileTable &t : b->rec_tables)
             if (t.dev) (void)hipFree(t.dev);
@@ -722,16 +740,33 @@ int rdcnn_batch_step_record(rdcnn_batch_t b, long long T, float *traj)
         const TileTable *t = nullptr;
         int rc = table_in(b, b->rec_tables, cpl, k, seg, false, &t);
         if (rc != RDCNN_OK) return rc;
-        hipError_t e = rd::launch_batch(t->dev, b->insts_dev, t->ntiles, b->buf[b->cur],
-                                        b->buf[1 - b->cur], b->bc, cpl, k, b->stream,
-                                        traj + q * b->total, (unsigned)(4 * b->total));
-        if (e != hipSuccess)
-            return bfail(RDCNN_EHIP, "rdcnn_batch_step_record: %s", hipGetErrorString(e));
+        hipError_t e;
+        if (even && q % 2 == 1)  // depth-1 passes: odd times are not kept
+            e = rd::launch_batch(t->dev, b->insts_dev, t->ntiles, b->buf[b->cur],
+                                 b->buf[1 - b->cur], b->bc, cpl, k, b->stream);
+        else
+            e = rd::launch_batch(t->dev, b->insts_dev, t->ntiles, b->buf[b->cur],
+                                 b->buf[1 - b->cur], b->bc, cpl, k, b->stream,
+                                 traj + (even ? q / 2 : q) * b->total, (unsigned)(4 * b->total),
+                                 even);
+        if (e != hipSuccess) return bfail(RDCNN_EHIP, "%s: %s", who, hipGetErrorString(e));
         b->cur = 1 - b->cur;
         q += k;
         T -= k;
     }
     return RDCNN_OK;
+}
+
+}  // namespace
+
+int rdcnn_batch_step_record(rdcnn_batch_t b, long long T, float *traj)
+{
+    return batch_record(b, T, traj, false, "rdcnn_batch_step_record");
+}
+
+int rdcnn_batch_step_record_even(rdcnn_batch_t b, long long T, float *traj)
+{
+    return batch_record(b, T, traj, true, "rdcnn_batch_step_record_even");
 }
 
 int rdcnn_batch_set_adjoint_kernel(rdcnn_batch_t b, int depth, int cols_per_lane, int seg_rows)
@@ -794,6 +829,64 @@ int rdcnn_batch_adjoint(rdcnn_batch_t b, const float *traj, long long S, float *
         e = rd::launch_batch_adjoint_finish(b->adj_partial, b->adj_first, b->adj_tiles_of,
                                             b->insts_dev, b->n, mask, dtheta, b->stream);
     if (e != hipSuccess) return bfail(RDCNN_EHIP, "rdcnn_batch_adjoint: %s", hipGetErrorString(e));
+    return RDCNN_OK;
+}
+
+int rdcnn_batch_adjoint_even(rdcnn_batch_t b, const float *traj, long long S, float *adj,
+                             float *adj_tmp, unsigned mask, double *dtheta)
+{
+    if (!b) return bfail(RDCNN_EINVAL, "rdcnn_batch_adjoint_even: NULL handle");
+    if (S < 0) return bfail(RDCNN_EINVAL, "rdcnn_batch_adjoint_even: S = %lld < 0", S);
+    if (!adj || !adj_tmp || !dtheta || (S > 0 && !traj))
+        return bfail(RDCNN_EINVAL, "rdcnn_batch_adjoint_even: NULL buffer");
+    if (adj == adj_tmp)
+        return bfail(RDCNN_EINVAL, "rdcnn_batch_adjoint_even: adj and adj_tmp alias");
+    if (b->adj_depth < 2)
+        return bfail(RDCNN_EINVAL, "rdcnn_batch_adjoint_even: paired passes need an adjoint "
+                     "depth of 2, 4 or 8 (rdcnn_batch_set_adjoint_kernel)");
+    // deepest paired pass whose depth/2 even states fit one buffer resource
+    int kmax = b->adj_depth;
+    const int cap = state_depth_cap(b, kmax / 2);
+    if (cap < 1) return bfail(RDCNN_EINVAL, "rdcnn_batch_adjoint_even: packed state too large");
+    while (kmax > 2 && kmax / 2 > cap) kmax >>= 1;
+    if (!b->adj_partial) {
+        const int rc = setup_adj(b);
+        if (rc != RDCNN_OK) return rc;
+    }
+    const int ntiles = b->adj_table.ntiles;
+    hipError_t e = rd::launch_zero(b->adj_partial, (long long)rd::kAdjSums * (ntiles + 1), b->stream);
+    const bool lam_sums = (mask & ((1u << 0) | (1u << 4) | (1u << 5))) != 0;
+    float *src = adj, *dst = adj_tmp;
+    auto flip = [&]() {
+        float *x = src;
+        src = dst;
+        dst = x;
+    };
+    if (e == hipSuccess && (S & 1) && ntiles > 0) {  // the top step alone: s_{S-1} is even
+        e = rd::launch_batch_adjoint(b->adj_table.dev, b->insts_dev, ntiles, src, dst,
+                                     traj + (S - 1) / 2 * b->total, (unsigned)(4 * b->total),
+                                     b->bc, b->adj_cpl, 1, b->adj_depth, b->adj_partial, lam_sums,
+                                     b->stream);
+        flip();
+    }
+    long long top = S & ~1LL;  // even time the next paired pass starts from
+    while (e == hipSuccess && top > 0 && ntiles > 0) {
+        int k = kmax;
+        while (k > 2 && k > top) k >>= 1;
+        e = rd::launch_batch_adjoint(b->adj_table.dev, b->insts_dev, ntiles, src, dst,
+                                     traj + (top - k) / 2 * b->total, (unsigned)(4 * b->total),
+                                     b->bc, b->adj_cpl, k, b->adj_depth, b->adj_partial, lam_sums,
+                                     b->stream, true);
+        flip();
+        top -= k;
+    }
+    if (e == hipSuccess && src != adj)
+        e = hipMemcpyAsync(adj, src, sizeof(float) * b->total, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess)
+        e = rd::launch_batch_adjoint_finish(b->adj_partial, b->adj_first, b->adj_tiles_of,
+                                            b->insts_dev, b->n, mask, dtheta, b->stream);
+    if (e != hipSuccess)
+        return bfail(RDCNN_EHIP, "rdcnn_batch_adjoint_even: %s", hipGetErrorString(e));
     return RDCNN_OK;
 }
 

@@ -84,7 +84,7 @@ hipError_t launch_naive(const float *in, float *out, int R, int C, int bc, const
 
 // ---------------------------------------------------------------- streamed
 
-template <int CPL, int K, bool REC>
+template <int CPL, int K, int REC>
 __global__ __launch_bounds__(64) void stream_step_kernel(StreamArgs A)
 {
     Tile<CPL> t;
@@ -131,7 +131,7 @@ namespace {
 
 using StreamFn = void (*)(StreamArgs);
 
-template <int CPL, bool REC, int... Ks>
+template <int CPL, int REC, int... Ks>
 constexpr StreamFn pick(int k, std::integer_sequence<int, Ks...>)
 {
     StreamFn f = nullptr;
@@ -139,9 +139,14 @@ constexpr StreamFn pick(int k, std::integer_sequence<int, Ks...>)
     return f;
 }
 
-template <bool REC>
+template <int REC>
 StreamFn pick_stream(int cpl, int depth)
 {
+    if (REC == 2) {  // even-state recording: one or two columns per lane, depth <= 8
+        if (cpl == 2) return pick<2, REC>(depth, std::make_integer_sequence<int, 8>{});
+        if (cpl == 1) return pick<1, REC>(depth, std::make_integer_sequence<int, 8>{});
+        return nullptr;
+    }
     if (cpl == 4) return pick<4, REC>(depth, std::make_integer_sequence<int, kMaxDepthCpl4>{});
     if (cpl == 2) return pick<2, REC>(depth, std::make_integer_sequence<int, kMaxDepthCpl2>{});
     if (cpl == 1) return pick<1, REC>(depth, std::make_integer_sequence<int, kMaxDepthCpl1>{});
@@ -167,10 +172,12 @@ TileArgs tile_args(int R, int C, int bc, const StreamGeom &geom)
 }
 
 hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, const Gene &g,
-                         const StreamGeom &geom, hipStream_t s, float *rec, long long rec_q0)
+                         const StreamGeom &geom, hipStream_t s, float *rec, long long rec_q0,
+                         bool rec_even)
 {
-    StreamFn f = rec ? pick_stream<true>(geom.cpl, geom.depth)
-                     : pick_stream<false>(geom.cpl, geom.depth);
+    StreamFn f = !rec ? pick_stream<0>(geom.cpl, geom.depth)
+                      : rec_even ? pick_stream<2>(geom.cpl, geom.depth)
+                                 : pick_stream<1>(geom.cpl, geom.depth);
     if (!f) return hipErrorInvalidValue;
     StreamArgs a;
     a.t = tile_args(R, C, bc, geom);

@@ -31,7 +31,10 @@ using StreamArgs = StreamArgsT<ModelFHN>;
 
 // ROWS_IN: every row the tile reads lies inside the grid, so row offsets need
 // no boundary mapping (true for all but the first and last segment of a strip).
-template <class M, int CPL, int K, bool REC, bool FAST, bool ROWS_IN>
+// REC: 0 no recording; 1 record every level (states q0 .. q0+K-1 of the pass);
+// 2 record the even levels only (the pass starts at an even time q0; level j
+// goes to recorded state j/2), for the reverse pass that rebuilds odd states.
+template <class M, int CPL, int K, int REC, bool FAST, bool ROWS_IN>
 __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<CPL> &t)
 {
     const int C = A.t.C, R = A.t.R, bc = A.t.bc;
@@ -39,9 +42,10 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
     const unsigned rowb = 4u * (unsigned)C;
     const Buf iu(A.in, pbytes), iv(A.in + (size_t)R * C, pbytes);
     const Buf ou(A.out, pbytes), ov(A.out + (size_t)R * C, pbytes);
-    // K recorded states, u plane then v plane each: state j at byte j*rec_stride.
+    // Recorded states, u plane then v plane each: state j at byte j*rec_stride.
+    constexpr int kRecLast = REC == 2 ? (K - 1) / 2 : K - 1;  // last recorded state of a pass
     const unsigned rstride = A.rec_stride;
-    const Buf rb(REC ? A.rec : A.in, REC ? (unsigned)(K - 1) * rstride + 2u * pbytes : 0u);
+    const Buf rb(REC ? A.rec : A.in, REC ? (unsigned)kRecLast * rstride + 2u * pbytes : 0u);
     const typename M::Params g = A.g;
     const int y0 = t.y0, y1 = t.y1;
 
@@ -142,10 +146,12 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
                     }
                 }
             }
-            if (REC && j + 1 < K && it >= 2 * j + 2 && it < n_real) {
+            if (REC && j + 1 < K && (REC == 1 || (j + 1) % 2 == 0) && it >= 2 * j + 2 &&
+                it < n_real) {
                 const int m = rbase + it - j - 1;  // level-(j+1) row just made
                 if (m >= y0 && m < y1) {
-                    const unsigned o = (unsigned)(j + 1) * rstride + 4u * (unsigned)m * C;
+                    const unsigned o = (unsigned)(REC == 2 ? (j + 1) / 2 : j + 1) * rstride +
+                                       4u * (unsigned)m * C;
                     store_row<CPL, FAST>(rb, o, C, t, bu[j + 1][sl.cs]);
                     store_row<CPL, FAST>(rb, o + pbytes, C, t, bv[j + 1][sl.cs]);
                 }

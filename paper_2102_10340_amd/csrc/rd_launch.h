@@ -59,10 +59,12 @@ hipError_t launch_naive(const float *in, float *out, int R, int C, int bc, const
 
 // `geom.depth` steps in one pass of the register-streamed kernel.  If rec is
 // not null, the states the pass steps from (levels 0..depth-1) are also written
-// to rec + (rec_q0 + j) * 2*R*C.
+// to rec + (rec_q0 + j) * 2*R*C; with rec_even only the even levels, level j to
+// rec + (rec_q0 + j/2) * 2*R*C (the pass must start at an even time; cpl 1 or
+// 2, depth <= 8).
 hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, const Gene &g,
                          const StreamGeom &geom, hipStream_t s, float *rec = nullptr,
-                         long long rec_q0 = 0);
+                         long long rec_q0 = 0, bool rec_even = false);
 
 // Cell models other than FitzHugh-Nagumo on the same streamed kernel
 // (rd_models.h).  Their passes take depth 1, 2, 4 or 8 and cols_per_lane 1 or 2.
@@ -86,6 +88,13 @@ hipError_t launch_cnn_input(const float *img, const float *bz, int R, int C, int
 hipError_t launch_adjoint(const float *in, float *out, const float *states, long long q_top,
                           int R, int C, int bc, const Gene &g, const StreamGeom &geom,
                           double *partial, bool lam_sums, hipStream_t s);
+// A paired pass: `geom.depth` (2, 4, 6 or 8; cpl 1 or 2) reverse steps from the
+// even time t_top, reading the even-time trajectory even_states (state s_{2i}
+// at index i) and rebuilding the odd states it needs.
+hipError_t launch_adjoint_pair(const float *in, float *out, const float *even_states,
+                               long long t_top, int R, int C, int bc, const Gene &g,
+                               const StreamGeom &geom, double *partial, bool lam_sums,
+                               hipStream_t s);
 
 hipError_t launch_zero(double *p, long long n, hipStream_t s);
 
@@ -110,18 +119,21 @@ struct BatchTile {
 // One launch of the batched kernel: `depth` steps for every tile of the list.
 // With rec, the states the pass steps from also go to the packed trajectory:
 // level j of instance i to rec + j * rec_stride bytes + its offset (recording
-// passes: cpl 1 or 2, depth <= 8).
+// passes: cpl 1 or 2, depth <= 8); with rec_even only the even levels, level j
+// to rec + (j/2) * rec_stride bytes (the pass starts at an even time).
 hipError_t launch_batch(const BatchTile *tiles, const BatchInst *insts, int ntiles,
                         const float *in, float *out, int bc, int cpl, int depth, hipStream_t s,
-                        float *rec = nullptr, unsigned rec_stride = 0);
+                        float *rec = nullptr, unsigned rec_stride = 0, bool rec_even = false);
 
 // Batched reverse pass: `depth` (1, 2, 4 or 8) reverse steps for every tile,
 // cpl 1 or 2; states = packed state q_top-depth+1, state_stride bytes apart.
 // The tile list was cut for table_depth >= depth (its halo is used as is).
+// paired: a paired pass (depth 2, 4 or 8) over an even-time trajectory; states
+// = the packed even state s_{t_top-depth}, the oldest the pass reads.
 hipError_t launch_batch_adjoint(const BatchTile *tiles, const BatchInst *insts, int ntiles,
                                 const float *in, float *out, const float *states,
                                 unsigned state_stride, int bc, int cpl, int depth, int table_depth,
-                                double *partial, bool lam_sums, hipStream_t s);
+                                double *partial, bool lam_sums, hipStream_t s, bool paired = false);
 // Per-instance gradients from the per-tile partials (tiles of instance i:
 // tiles_of[first[i] .. first[i+1])), added to dtheta[8 i ..].
 hipError_t launch_batch_adjoint_finish(const double *partial, const int *first, const int *tiles_of,

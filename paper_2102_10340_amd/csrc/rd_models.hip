@@ -16,11 +16,11 @@ __global__ __launch_bounds__(64) void model_step_kernel(StreamArgsT<M> A)
     if (!t.init(A.t)) return;
     if (t.fast) {
         if (t.y0 >= K && t.y1 + K <= A.t.R)
-            stream_body<M, CPL, K, false, true, true>(A, t);
+            stream_body<M, CPL, K, 0, true, true>(A, t);
         else
-            stream_body<M, CPL, K, false, true, false>(A, t);
+            stream_body<M, CPL, K, 0, true, false>(A, t);
     } else {
-        stream_body<M, CPL, K, false, false, false>(A, t);
+        stream_body<M, CPL, K, 0, false, false>(A, t);
     }
 }
 

@@ -100,6 +100,15 @@ class Simulation:
         check(lib.rdcnn_step_record(self._h, int(T), states.data_ptr() if T > 0 else None))
         return self
 
+    def step_record_even(self, T: int, states: torch.Tensor) -> "Simulation":
+        """Advance by T steps keeping only the even-time states: s_{2i} goes to
+        states[i] for 2i < T (shape [>= (T+1)//2, 2, R, C]); the trajectory
+        adjoint_even reads."""
+        if T > 0:
+            self._check_states(states, (T + 1) // 2)
+        check(lib.rdcnn_step_record_even(self._h, int(T), states.data_ptr() if T > 0 else None))
+        return self
+
     def adjoint(self, states: torch.Tensor, S: int, adj: torch.Tensor, adj_tmp: torch.Tensor,
                 dtheta: torch.Tensor) -> None:
         """Reverse pass through S steps recorded in states[0..S-1]: adj [2, R, C]
@@ -107,13 +116,26 @@ class Simulation:
         order dt, a, b, eps, c, k3, Du, Dv) is added to dtheta."""
         if S > 0:
             self._check_states(states, S)
+        self._check_adjoint(adj, adj_tmp, dtheta)
+        check(lib.rdcnn_adjoint(self._h, states.data_ptr() if S > 0 else None, int(S),
+                                adj.data_ptr(), adj_tmp.data_ptr(), dtheta.data_ptr()))
+
+    def adjoint_even(self, states: torch.Tensor, S: int, adj: torch.Tensor, adj_tmp: torch.Tensor,
+                     dtheta: torch.Tensor) -> None:
+        """adjoint() from an even-time trajectory (step_record_even): the odd
+        states are rebuilt inside the reverse passes; same results."""
+        if S > 0:
+            self._check_states(states, (S + 1) // 2)
+        self._check_adjoint(adj, adj_tmp, dtheta)
+        check(lib.rdcnn_adjoint_even(self._h, states.data_ptr() if S > 0 else None, int(S),
+                                     adj.data_ptr(), adj_tmp.data_ptr(), dtheta.data_ptr()))
+
+    def _check_adjoint(self, adj, adj_tmp, dtheta):
         for t in (adj, adj_tmp):
             if t.shape != (2, self.rows, self.cols) or t.dtype != torch.float32 or not t.is_contiguous():
                 raise ValueError("adjoint buffers must be contiguous float32 [2, R, C]")
         if dtheta.dtype != torch.float64 or dtheta.numel() != 8 or not dtheta.is_cuda:
             raise ValueError("dtheta must be a CUDA float64 tensor of 8 elements")
-        check(lib.rdcnn_adjoint(self._h, states.data_ptr() if S > 0 else None, int(S),
-                                adj.data_ptr(), adj_tmp.data_ptr(), dtheta.data_ptr()))
 
     def set_grad_mask(self, mask: int) -> None:
         """Parameter gradients the adjoint forms (bit q = parameter q in the order
