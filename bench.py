@@ -481,7 +481,7 @@ def main():
     launch_s = ms / 1e3 / launches  # upper bound: includes the snapshot copies
     achieved_gbs = BYTES_PER_CELL_UPDATE * R * C * depth / launch_s / 1e9
     alive = float(snaps[-1, 0].abs().max())
-    traffic = measured_traffic(f"void rd::stream_step_kernel<4, {depth}, false>")
+    traffic = measured_traffic(f"void rd::stream_step_kernel<4, {depth}, 0>")
 
     out = {
         "metric": "Gcell-updates/s FP32 forward (slow-growth 4096^2) + % of HBM roofline",
@@ -499,7 +499,7 @@ def main():
         "config": {"workload": "slow-growth 4096x4096 zero-flux, 16x16 random centre patch, "
                                "dt=0.1 Du=0.05 Dv=1 f1=u-u^3-v f2=0.1(u-v), T=10000 per step + "
                                "device snapshot", "time_steps_per_step": chunk,
-                   "grid": [R, C], "kernel": f"stream_step_kernel<4,{depth},false>",
+                   "grid": [R, C], "kernel": f"stream_step_kernel<4,{depth},0>",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,

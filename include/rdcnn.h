@@ -188,8 +188,12 @@ int rdcnn_step_record(rdcnn_t h, long long T, float *states_dev);
  *               parameters of the gradient mask (rdcnn_set_grad_mask; default
  *               all), NaN for the others
  * Uses the handle's current parameters, boundary rule and stream.  S == 0 does
- * nothing.  The first call on a handle allocates a small device workspace for
- * per-tile partial sums (8 doubles per tile; freed by rdcnn_destroy).  Results
+ * nothing.  A call takes a small device workspace for per-tile partial sums
+ * (8 doubles per tile) from a process-wide pool, allocating one the first time;
+ * rdcnn_destroy returns it to the pool (at most 16 buffers, kept until the
+ * process ends), and a later user's stream is ordered after this handle's
+ * work on it by an event, so handles can come and go without allocating or
+ * synchronizing.  Results
  * are deterministic (fixed reduction order).  Asynchronous.
  * Errors: RDCNN_EINVAL, RDCNN_ENOMEM (workspace), RDCNN_EHIP.
  */

@@ -90,8 +90,11 @@ def _backward(sim: Simulation, ckpt, nseg: int, T: int, S: int, gu, gv, dev, ker
               mask: int = 0xFF):
     R, C = sim.rows, sim.cols
     adj = torch.empty((2, R, C), dtype=torch.float32, device=dev)
-    adj[0].copy_(gu if gu is not None else torch.zeros((R, C), device=dev))
-    adj[1].copy_(gv if gv is not None else torch.zeros((R, C), device=dev))
+    for k, gk in enumerate((gu, gv)):
+        if gk is None:
+            adj[k].zero_()
+        else:
+            adj[k].copy_(gk)
     tmp = torch.empty_like(adj)
     dtheta = torch.zeros(8, dtype=torch.float64, device=dev)
     if kernel is not None:

@@ -92,8 +92,9 @@ __device__ __forceinline__ void add_tile_sums(const AdjArgs &A, const Tile<CPL> 
     }
 }
 
-// ROWS_IN: every row the tile reads lies inside the grid, so row offsets need
-// no boundary mapping.
+// ROWS_IN: every row the tile reads, including the kFetchPast rows fetched
+// past the end of its walk, lies inside the grid, so row offsets need no
+// boundary mapping.
 template <int CPL, int KB, bool FAST, bool ROWS_IN, bool LAMS>
 __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &t)
 {
@@ -159,8 +160,8 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &
                 const float rl = from_right_lane(bl[i][sl.cs][0]);
                 const float lm = from_left_lane(bm[i][sl.cs][CPL - 1]);
                 const float rm = from_right_lane(bm[i][sl.cs][0]);
-                // uniform; readfirstlane keeps the branch on the scalar unit
-                const int count = __builtin_amdgcn_readfirstlane((int)(m >= y0 && m < y1));
+                // uniform (m, y0, y1 are scalars): a scalar compare and branch
+                const int count = m >= y0 && m < y1;
 #pragma unroll
                 for (int e = 0; e < CPL; ++e) {
                     const float l = bl[i][sl.cs][e], mu = bm[i][sl.cs][e];
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs A)
     Tile<CPL> t;
     if (!t.init(A.t)) return;
     if (t.fast) {
-        if (t.y0 >= KB && t.y1 + KB <= A.t.R)
+        if (t.y0 >= KB && t.y1 + KB + kFetchPast <= A.t.R)
             adjoint_body<CPL, KB, true, true, LAMS>(A, t);
         else
             adjoint_body<CPL, KB, true, false, LAMS>(A, t);
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs A)
 template <int CPL, int KB, bool FAST, bool ROWS_IN, bool LAMS, int DL, int DE>
 __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<CPL> &t)
 {
-    static_assert(KB % 2 == 0 && DL >= 1 && DL <= 3 && DE >= 1 && DE <= 3, "pass shape");
+    static_assert(KB % 2 == 0 && DL >= 1 && DL <= kFetchPast && DE >= 1 && DE <= 3, "pass shape");
     constexpr int P = KB / 2;
     const int C = A.t.C, R = A.t.R, bc = A.t.bc;
     const unsigned pbytes = 4u * (unsigned)R * (unsigned)C;
@@ -356,7 +357,7 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
                 const float rl = from_right_lane(lC[0]);
                 const float lm = from_left_lane(mC[CPL - 1]);
                 const float rm = from_right_lane(mC[0]);
-                const int count = __builtin_amdgcn_readfirstlane((int)(m >= y0 && m < y1));
+                const int count = m >= y0 && m < y1;
 #pragma unroll
                 for (int e = 0; e < CPL; ++e) {
                     const float lW = e == 0 ? ll : lC[e - 1];
@@ -427,7 +428,7 @@ __global__ __launch_bounds__(64) void adjoint_pair_kernel(AdjArgs A)
     Tile<CPL> t;
     if (!t.init(A.t)) return;
     if (t.fast) {
-        if (t.y0 >= KB && t.y1 + KB <= A.t.R)
+        if (t.y0 >= KB && t.y1 + KB + kFetchPast <= A.t.R)
             adjoint_pair_body<CPL, KB, true, true, LAMS, kPairDL, kPairDE>(A, t);
         else
             adjoint_pair_body<CPL, KB, true, false, LAMS, kPairDL, kPairDE>(A, t);
@@ -512,7 +513,7 @@ __global__ __launch_bounds__(64) void batch_adjoint_kernel(BatchAdjArgs B)
     Tile<CPL> t;
     batch_tile_args<CPL>(B, id, A, t);
     if (t.fast) {
-        if (t.y0 >= KB && t.y1 + KB <= A.t.R)
+        if (t.y0 >= KB && t.y1 + KB + kFetchPast <= A.t.R)
             adjoint_body<CPL, KB, true, true, LAMS>(A, t);
         else
             adjoint_body<CPL, KB, true, false, LAMS>(A, t);
@@ -532,7 +533,7 @@ __global__ __launch_bounds__(64) void batch_adjoint_pair_kernel(BatchAdjArgs B)
     Tile<CPL> t;
     batch_tile_args<CPL>(B, id, A, t);
     if (t.fast) {
-        if (t.y0 >= KB && t.y1 + KB <= A.t.R)
+        if (t.y0 >= KB && t.y1 + KB + kFetchPast <= A.t.R)
             adjoint_pair_body<CPL, KB, true, true, LAMS, kPairDL, kPairDE>(A, t);
         else
             adjoint_pair_body<CPL, KB, true, false, LAMS, kPairDL, kPairDE>(A, t);

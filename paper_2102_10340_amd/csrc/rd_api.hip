@@ -9,7 +9,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "rd_launch.h"
 #include "rdcnn.h"
@@ -24,8 +26,9 @@ struct rdcnn_sim {
     int depth, cpl, seg_rows;
     int adj_depth, adj_cpl, adj_seg_rows;  // 0: automatic
     unsigned grad_mask;                    // gradients rdcnn_adjoint forms (bit q: param q)
-    double *partial;                       // adjoint per-tile partial sums
+    double *partial;                       // adjoint per-tile partial sums (pooled)
     long long partial_cap;                 // tiles it can hold
+    int partial_device;                    // device it lives on
     int model;                             // rd::MODEL_*; g holds the FHN gene
     float mparams[rd::kModelParams];       // parameters of the other models
 };
@@ -50,6 +53,97 @@ namespace {
 int hip_fail(hipError_t e, const char *what)
 {
     return fail(RDCNN_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// The adjoint's per-tile partial sums (a few hundred KB) come from a
+// process-wide pool: a handle returns its buffer on destroy instead of freeing
+// it, so short-lived handles (one per autograd call) allocate nothing after the
+// first and never call hipFree, which would wait for the whole device.  A
+// returned buffer carries an event recorded on its last user's stream; the
+// next user's stream waits for it, so work still queued on the old stream
+// finishes with the buffer first.  Pooled buffers stay allocated until the
+// process ends.
+struct PooledPartial {
+    int device;
+    long long cap;      // tiles
+    double *p;
+    hipEvent_t ready;   // the last user's work on it is done (null: nothing queued)
+};
+std::mutex g_pool_mu;
+std::vector<PooledPartial> g_pool;
+constexpr size_t kPoolMax = 16;
+
+void release_entry(PooledPartial &x)
+{
+    (void)hipFree(x.p);  // waits for the device, so also for x.ready
+    if (x.ready) (void)hipEventDestroy(x.ready);
+}
+
+void pool_put(int device, long long cap, double *p, hipStream_t last_user)
+{
+    if (!p) return;
+    PooledPartial x{device, cap, p, nullptr};
+    if (hipEventCreateWithFlags(&x.ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(x.ready, last_user) != hipSuccess) {
+        if (x.ready) (void)hipEventDestroy(x.ready);
+        x.ready = nullptr;
+        (void)hipStreamSynchronize(last_user);
+    }
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if (g_pool.size() >= kPoolMax) {  // keep the larger buffers
+        size_t k = 0;
+        for (size_t i = 1; i < g_pool.size(); ++i)
+            if (g_pool[i].cap < g_pool[k].cap) k = i;
+        if (g_pool[k].cap >= cap) {
+            release_entry(x);
+            return;
+        }
+        release_entry(g_pool[k]);
+        g_pool.erase(g_pool.begin() + (long)k);
+    }
+    g_pool.push_back(x);
+}
+
+// Make h->partial hold at least `need` tiles on the current device.
+int ensure_partial(rdcnn_sim *h, long long need, const char *who)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, who);
+    if (h->partial && h->partial_cap >= need && h->partial_device == dev) return RDCNN_OK;
+    pool_put(h->partial_device, h->partial_cap, h->partial, h->stream);
+    h->partial = nullptr;
+    h->partial_cap = 0;
+    hipEvent_t ready = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_pool_mu);
+        long long best = -1;
+        for (size_t i = 0; i < g_pool.size(); ++i)
+            if (g_pool[i].device == dev && g_pool[i].cap >= need &&
+                (best < 0 || g_pool[i].cap < g_pool[(size_t)best].cap))
+                best = (long long)i;
+        if (best >= 0) {
+            h->partial = g_pool[(size_t)best].p;
+            h->partial_cap = g_pool[(size_t)best].cap;
+            ready = g_pool[(size_t)best].ready;
+            g_pool.erase(g_pool.begin() + best);
+        }
+    }
+    if (ready) {  // queued after the previous user's work on the buffer
+        e = hipStreamWaitEvent(h->stream, ready, 0);
+        (void)hipEventDestroy(ready);
+        if (e != hipSuccess) return hip_fail(e, who);
+    }
+    if (!h->partial) {
+        e = hipMalloc((void **)&h->partial, sizeof(double) * rd::kAdjSums * need);
+        if (e != hipSuccess) {
+            h->partial = nullptr;
+            return fail(RDCNN_ENOMEM, "%s: partial buffer: %s", who, hipGetErrorString(e));
+        }
+        h->partial_cap = need;
+    }
+    h->partial_device = dev;
+    return RDCNN_OK;
 }
 
 bool finite_params(const rdcnn_params_t *p)
@@ -262,6 +356,7 @@ rdcnn_sim *new_sim(int rows, int cols, int bc, float *buf0, float *buf1, void *s
     h->grad_mask = 0xFFu;
     h->partial = nullptr;
     h->partial_cap = 0;
+    h->partial_device = 0;
     h->model = rd::MODEL_FHN;
     for (float &x : h->mparams) x = 0.0f;
     return h;
@@ -409,16 +504,9 @@ int rdcnn_adjoint(rdcnn_t h, const float *states_dev, long long S, float *adj_de
         !rd::stream_geometry(h->R, h->C, cpl, klast, seg, &glast))
         return fail(RDCNN_EINVAL, "rdcnn_adjoint: cannot tile %dx%d", h->R, h->C);
     const long long need = gfull.ntiles > glast.ntiles ? gfull.ntiles : glast.ntiles;
-    if (need > h->partial_cap) {
-        if (h->partial) (void)hipFree(h->partial);
-        h->partial = nullptr;
-        h->partial_cap = 0;
-        hipError_t e = hipMalloc((void **)&h->partial, sizeof(double) * rd::kAdjSums * need);
-        if (e != hipSuccess) {
-            h->partial = nullptr;
-            return fail(RDCNN_ENOMEM, "rdcnn_adjoint: partial buffer: %s", hipGetErrorString(e));
-        }
-        h->partial_cap = need;
+    {
+        const int rc = ensure_partial(h, need, "rdcnn_adjoint");
+        if (rc != RDCNN_OK) return rc;
     }
     hipError_t e = rd::launch_zero(h->partial, rd::kAdjSums * need, h->stream);
     if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint: zero");
@@ -484,17 +572,9 @@ int rdcnn_adjoint_even(rdcnn_t h, const float *states_dev, long long S, float *a
             return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: cannot tile %dx%d", h->R, h->C);
         if (gk.ntiles > need) need = gk.ntiles;
     }
-    if (need > h->partial_cap) {
-        if (h->partial) (void)hipFree(h->partial);
-        h->partial = nullptr;
-        h->partial_cap = 0;
-        hipError_t e = hipMalloc((void **)&h->partial, sizeof(double) * rd::kAdjSums * need);
-        if (e != hipSuccess) {
-            h->partial = nullptr;
-            return fail(RDCNN_ENOMEM, "rdcnn_adjoint_even: partial buffer: %s",
-                        hipGetErrorString(e));
-        }
-        h->partial_cap = need;
+    {
+        const int rc = ensure_partial(h, need, "rdcnn_adjoint_even");
+        if (rc != RDCNN_OK) return rc;
     }
     hipError_t e = rd::launch_zero(h->partial, rd::kAdjSums * need, h->stream);
     if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint_even: zero");
@@ -619,7 +699,7 @@ int rdcnn_set_kernel(rdcnn_t h, int kind, int depth, int cols_per_lane, int seg_
 int rdcnn_destroy(rdcnn_t h)
 {
     if (!h) return RDCNN_OK;
-    if (h->partial) (void)hipFree(h->partial);
+    pool_put(h->partial_device, h->partial_cap, h->partial, h->stream);
     delete h;
     return RDCNN_OK;
 }

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(64) void batch_step_kernel(BatchArgs B)
     Tile<CPL> t;
     t.setup(A.t, id, bt.x0, bt.y0, bt.y1);
     if (t.fast) {
-        if (t.y0 >= K && t.y1 + K <= in.R)
+        if (t.y0 >= K && t.y1 + K + kFetchPast <= in.R)
             stream_body<ModelFHN, CPL, K, REC, true, true>(A, t);
         else
             stream_body<ModelFHN, CPL, K, REC, true, false>(A, t);

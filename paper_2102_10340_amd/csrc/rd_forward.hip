@@ -90,7 +90,7 @@ __global__ __launch_bounds__(64) void stream_step_kernel(StreamArgs A)
     Tile<CPL> t;
     if (!t.init(A.t)) return;
     if (t.fast) {
-        if (t.y0 >= K && t.y1 + K <= A.t.R)
+        if (t.y0 >= K && t.y1 + K + kFetchPast <= A.t.R)
             stream_body<ModelFHN, CPL, K, REC, true, true>(A, t);
         else
             stream_body<ModelFHN, CPL, K, REC, true, false>(A, t);

@@ -29,8 +29,9 @@ struct StreamArgsT {
 };
 using StreamArgs = StreamArgsT<ModelFHN>;
 
-// ROWS_IN: every row the tile reads lies inside the grid, so row offsets need
-// no boundary mapping (true for all but the first and last segment of a strip).
+// ROWS_IN: every row the tile reads, including the kFetchPast rows fetched
+// past the end of its walk, lies inside the grid, so row offsets need no
+// boundary mapping (true for all but the first and last segments of a strip).
 // REC: 0 no recording; 1 record every level (states q0 .. q0+K-1 of the pass);
 // 2 record the even levels only (the pass starts at an even time q0; level j
 // goes to recorded state j/2), for the reverse pass that rebuilds odd states.

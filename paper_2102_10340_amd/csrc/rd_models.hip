@@ -15,7 +15,7 @@ __global__ __launch_bounds__(64) void model_step_kernel(StreamArgsT<M> A)
     Tile<CPL> t;
     if (!t.init(A.t)) return;
     if (t.fast) {
-        if (t.y0 >= K && t.y1 + K <= A.t.R)
+        if (t.y0 >= K && t.y1 + K + kFetchPast <= A.t.R)
             stream_body<M, CPL, K, 0, true, true>(A, t);
         else
             stream_body<M, CPL, K, 0, true, false>(A, t);

@@ -191,6 +191,13 @@ __device__ __forceinline__ unsigned row_off(int r, int R, int C, int bc)
     return 4u * (unsigned)map_index(r, R, bc) * (unsigned)C;
 }
 
+// A walk over rows rbase .. rbase+n_real-1 fetches up to this many rows past
+// its last one (row prefetches of the last iterations; nothing uses them).  A
+// tile takes the unmapped-row (ROWS_IN) path only if those rows are inside the
+// grid too: the row offset travels in a buffer instruction's scalar offset, so
+// every row it names must lie inside the plane.
+constexpr int kFetchPast = 3;
+
 // Slots of the three-row window of time level j while row `it` of level 0 is
 // read: row it-j (newest), it-j-1 (centre) and it-j-2 (oldest) of level j sit
 // in slots (S-j) mod 3, (S-j-1) mod 3 and (S-j-2) mod 3, S = it mod 3.
