@@ -18,6 +18,11 @@
 
 namespace rd {
 
+// Level-0 rows are fetched this many iterations before their first use
+// (at most kFetchPast: the last fetches name rows past the walk).
+constexpr int kFwdFetch = 2;
+static_assert(kFwdFetch >= 1 && kFwdFetch <= kFetchPast, "level-0 fetch distance");
+
 template <class M>
 struct StreamArgsT {
     TileArgs t;
@@ -50,82 +55,99 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
     const typename M::Params g = A.g;
     const int y0 = t.y0, y1 = t.y1;
 
-    const int rbase = y0 - K;                 // first row read (level 0)
-    const int n_real = y1 - y0 + 2 * K;       // rows walked
-    const int n_iter = (n_real + 2) / 3 * 3;  // ... padded to a multiple of 3
+    const int rbase = y0 - K;            // first row read (level 0)
+    const int n_real = y1 - y0 + 2 * K;  // rows walked
     auto roff = [&](int r) -> unsigned {
         return ROWS_IN ? (unsigned)r * rowb : row_off(r, R, C, bc);
     };
 
-    // Row q (counted from rbase) of time level j lives in slot q % 3 of level
-    // j.  Iteration `it` reads level-0 row it and makes level-(j+1) row it-j-1
-    // from level-j rows it-j-2, it-j-1, it-j; the new row overwrites the slot of
-    // level-(j+1) row it-j-4, which nothing needs any more.  With the loop
-    // unrolled three times every slot index is a compile-time constant, so the
-    // window rotates without register copies.
-    float bu[K][3][CPL], bv[K][3][CPL];
+    // Row q (counted from rbase) of time level j >= 1 lives in slot q % 3 of
+    // level j.  Iteration `it` makes level-(j+1) row it-j-1 from level-j rows
+    // it-j-2, it-j-1, it-j; the new row overwrites the slot of level-(j+1) row
+    // it-j-4, which nothing needs any more.  Level 0 (the rows read from HBM)
+    // has a six-slot ring instead: row q sits in slot q % 6 and is fetched
+    // kFwdFetch iterations before it is first used, so the wait for it does not
+    // also wait for the stores issued after it (vmcnt retires in issue order
+    // and counts stores too).  With the loop unrolled six times every slot
+    // index is a compile-time constant, so the windows rotate without
+    // register copies.
+    float l0u[6][CPL], l0v[6][CPL];
+    float bu[K][3][CPL], bv[K][3][CPL];  // levels 1 .. K-1 (index 0 unused)
 #pragma unroll
-    for (int j = 0; j < K; ++j)
+    for (int e = 0; e < CPL; ++e) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q)
+        for (int q = 0; q < 6; ++q) l0u[q][e] = l0v[q][e] = 0.0f;
 #pragma unroll
-            for (int e = 0; e < CPL; ++e) bu[j][q][e] = bv[j][q][e] = 0.0f;
-    {
-        const unsigned ro = roff(rbase);
-        load_row<CPL, FAST>(iu, ro, t, bu[0][0]);
-        load_row<CPL, FAST>(iv, ro, t, bv[0][0]);
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) bu[j][q][e] = bv[j][q][e] = 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < kFwdFetch; ++q) {
+        const unsigned ro = roff(rbase + q);
+        load_row<CPL, FAST>(iu, ro, t, l0u[q]);
+        load_row<CPL, FAST>(iv, ro, t, l0v[q]);
     }
 
-    auto iteration = [&](const int it, const int S) __attribute__((always_inline)) {
+    auto iteration = [&](const int it, const int S6) __attribute__((always_inline)) {
+        const int S = S6 % 3;
+        // level-0 ring slots of rows it-2 (north), it-1 (centre), it (south)
+        const int qN = (S6 + 4) % 6, qC = (S6 + 5) % 6, qS = S6;
         float tu[CPL], tv[CPL];  // row it-K of level K (the pass output)
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const Slots sl(S, j);
             float *du = j + 1 < K ? bu[j + 1][sl.cs] : tu;  // level j+1, row it-j-1
             float *dv = j + 1 < K ? bv[j + 1][sl.cs] : tv;
+            const float *uN = j == 0 ? l0u[qN] : bu[j][sl.ps];
+            const float *uC = j == 0 ? l0u[qC] : bu[j][sl.cs];
+            const float *uS = j == 0 ? l0u[qS] : bu[j][sl.ns];
+            const float *vN = j == 0 ? l0v[qN] : bv[j][sl.ps];
+            const float *vC = j == 0 ? l0v[qC] : bv[j][sl.cs];
+            const float *vS = j == 0 ? l0v[qS] : bv[j][sl.ns];
             // Level j+1 has all three input rows from it = 2j+2 on; rows made
             // after it = n_real are beyond the segment's cone.
             if (it >= 2 * j + 2 && it < n_real) {
                 // lane-shifted edge columns of the centre row (and, for models
                 // reading diagonals, of the north and south rows)
-                const float lu = from_left_lane(bu[j][sl.cs][CPL - 1]);
-                const float ru = from_right_lane(bu[j][sl.cs][0]);
-                const float lv = from_left_lane(bv[j][sl.cs][CPL - 1]);
-                const float rv = from_right_lane(bv[j][sl.cs][0]);
+                const float lu = from_left_lane(uC[CPL - 1]);
+                const float ru = from_right_lane(uC[0]);
+                const float lv = from_left_lane(vC[CPL - 1]);
+                const float rv = from_right_lane(vC[0]);
                 float luN = 0.0f, ruN = 0.0f, lvN = 0.0f, rvN = 0.0f;
                 float luS = 0.0f, ruS = 0.0f, lvS = 0.0f, rvS = 0.0f;
                 if (M::kDiag) {
-                    luN = from_left_lane(bu[j][sl.ps][CPL - 1]);
-                    ruN = from_right_lane(bu[j][sl.ps][0]);
-                    lvN = from_left_lane(bv[j][sl.ps][CPL - 1]);
-                    rvN = from_right_lane(bv[j][sl.ps][0]);
-                    luS = from_left_lane(bu[j][sl.ns][CPL - 1]);
-                    ruS = from_right_lane(bu[j][sl.ns][0]);
-                    lvS = from_left_lane(bv[j][sl.ns][CPL - 1]);
-                    rvS = from_right_lane(bv[j][sl.ns][0]);
+                    luN = from_left_lane(uN[CPL - 1]);
+                    ruN = from_right_lane(uN[0]);
+                    lvN = from_left_lane(vN[CPL - 1]);
+                    rvN = from_right_lane(vN[0]);
+                    luS = from_left_lane(uS[CPL - 1]);
+                    ruS = from_right_lane(uS[0]);
+                    lvS = from_left_lane(vS[CPL - 1]);
+                    rvS = from_right_lane(vS[0]);
                 }
 #pragma unroll
                 for (int e = 0; e < CPL; ++e) {
                     Nbhd n;
-                    n.u = bu[j][sl.cs][e];
-                    n.v = bv[j][sl.cs][e];
-                    n.uN = bu[j][sl.ps][e];
-                    n.uS = bu[j][sl.ns][e];
-                    n.vN = bv[j][sl.ps][e];
-                    n.vS = bv[j][sl.ns][e];
-                    n.uW = e == 0 ? lu : bu[j][sl.cs][e - 1];
-                    n.uE = e == CPL - 1 ? ru : bu[j][sl.cs][e + 1];
-                    n.vW = e == 0 ? lv : bv[j][sl.cs][e - 1];
-                    n.vE = e == CPL - 1 ? rv : bv[j][sl.cs][e + 1];
+                    n.u = uC[e];
+                    n.v = vC[e];
+                    n.uN = uN[e];
+                    n.uS = uS[e];
+                    n.vN = vN[e];
+                    n.vS = vS[e];
+                    n.uW = e == 0 ? lu : uC[e - 1];
+                    n.uE = e == CPL - 1 ? ru : uC[e + 1];
+                    n.vW = e == 0 ? lv : vC[e - 1];
+                    n.vE = e == CPL - 1 ? rv : vC[e + 1];
                     if (M::kDiag) {
-                        n.uNW = e == 0 ? luN : bu[j][sl.ps][e - 1];
-                        n.uNE = e == CPL - 1 ? ruN : bu[j][sl.ps][e + 1];
-                        n.vNW = e == 0 ? lvN : bv[j][sl.ps][e - 1];
-                        n.vNE = e == CPL - 1 ? rvN : bv[j][sl.ps][e + 1];
-                        n.uSW = e == 0 ? luS : bu[j][sl.ns][e - 1];
-                        n.uSE = e == CPL - 1 ? ruS : bu[j][sl.ns][e + 1];
-                        n.vSW = e == 0 ? lvS : bv[j][sl.ns][e - 1];
-                        n.vSE = e == CPL - 1 ? rvS : bv[j][sl.ns][e + 1];
+                        n.uNW = e == 0 ? luN : uN[e - 1];
+                        n.uNE = e == CPL - 1 ? ruN : uN[e + 1];
+                        n.vNW = e == 0 ? lvN : vN[e - 1];
+                        n.vNE = e == CPL - 1 ? rvN : vN[e + 1];
+                        n.uSW = e == 0 ? luS : uS[e - 1];
+                        n.uSE = e == CPL - 1 ? ruS : uS[e + 1];
+                        n.vSW = e == 0 ? lvS : vS[e - 1];
+                        n.vSE = e == CPL - 1 ? rvS : vS[e + 1];
                     }
                     M::update(g, n, du[e], dv[e]);
                 }
@@ -134,16 +156,17 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
             // vmcnt retires in issue order, so waiting for the load next
             // iteration then does not also wait for the stores.
             if (j == 0) {
-                // Level-0 row it-2 is spent: fetch row it+1 into its slot.
-                const unsigned ro = roff(rbase + it + 1);
-                load_row<CPL, FAST>(iu, ro, t, bu[0][sl.ps]);
-                load_row<CPL, FAST>(iv, ro, t, bv[0][sl.ps]);
+                // Fetch level-0 row it+kFwdFetch into the slot of row
+                // it+kFwdFetch-6, which no level reads any more.
+                const unsigned ro = roff(rbase + it + kFwdFetch);
+                load_row<CPL, FAST>(iu, ro, t, l0u[(S6 + kFwdFetch) % 6]);
+                load_row<CPL, FAST>(iv, ro, t, l0v[(S6 + kFwdFetch) % 6]);
                 if (REC) {
                     const int m = rbase + it;  // level-0 row it
                     if (m >= y0 && m < y1) {
                         const unsigned o = 4u * (unsigned)m * C;
-                        store_row<CPL, FAST>(rb, o, C, t, bu[0][sl.ns]);
-                        store_row<CPL, FAST>(rb, o + pbytes, C, t, bv[0][sl.ns]);
+                        store_row<CPL, FAST>(rb, o, C, t, l0u[qS]);
+                        store_row<CPL, FAST>(rb, o + pbytes, C, t, l0v[qS]);
                     }
                 }
             }
@@ -166,10 +189,20 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
         }
     };
 
-    for (int it = 0; it < n_iter; it += 3) {
+    // Iterations from n_real on would only fetch rows nobody reads: leave the
+    // unrolled body as soon as the walk is done (uniform branches).
+    for (int it = 0; it < n_real; it += 6) {
         iteration(it, 0);
+        if (it + 1 >= n_real) break;
         iteration(it + 1, 1);
+        if (it + 2 >= n_real) break;
         iteration(it + 2, 2);
+        if (it + 3 >= n_real) break;
+        iteration(it + 3, 3);
+        if (it + 4 >= n_real) break;
+        iteration(it + 4, 4);
+        if (it + 5 >= n_real) break;
+        iteration(it + 5, 5);
     }
 }
 
