@@ -28,16 +28,19 @@
  *   - Boundary: periodic (toroidal, as in all of the paper's kernels) or
  *     zero-flux, read as a ghost cell that copies the edge cell
  *     (u_{-1,j} = u_{0,j}, u_{R,j} = u_{R-1,j}, same for columns).
- *   - Rounding order (the paper does not state one).  Every cell is evaluated as
+ *   - Rounding order (the paper does not state one).  In float every cell is
+ *     evaluated as
  *       sU  = (uN + uS) + (uW + uE);      LU = fma(-4, u, sU)
  *       sV  = (vN + vS) + (vW + vE);      LV = fma(-4, v, sV)
- *       f1  = fma(-k3, (u*u)*u, fma(c, u, -v))
- *       f2  = (-eps) * (fma(-b, v, u) + a)
+ *       f1  = fma(u, fma(-k3, u*u, c), -v)             = c u - k3 u^3 - v
+ *       f2  = fma(eps*b, v, fma(-eps, u, -(eps*a)))    = -eps (u - b v + a)
  *       u+  = fma(dt, fma(Du, LU, f1), u)
  *       v+  = fma(dt, fma(Dv, LV, f2), v)
- *     in the working precision (float or double), fma being the correctly
- *     rounded fused multiply-add of C99.  The build uses -ffp-contract=off so
- *     that no other contraction happens, and no flush-to-zero.
+ *     (eps*b and eps*a rounded to float once), and in double with the
+ *     textbook grouping f1 = fma(-k3, (u*u)*u, fma(c, u, -v)),
+ *     f2 = (-eps) * (fma(-b, v, u) + a); fma is the correctly rounded fused
+ *     multiply-add of C99.  The build uses -ffp-contract=off so that no other
+ *     contraction happens, and no flush-to-zero.
  *
  * Reverse pass (gradient of a loss J(s_T) through the T steps), written from the
  * transpose of the Jacobian of the step above.  With lam' = dJ/du_{t+1},
@@ -90,8 +93,8 @@ static void step_f32(long R, long C, int bc, const float p[8],
             const float sV = (v[iN * C + j] + v[iS * C + j]) + (v[i * C + jW] + v[i * C + jE]);
             const float LU = fmaf(-4.0f, uc, sU);
             const float LV = fmaf(-4.0f, vc, sV);
-            const float f1 = fmaf(-k3, (uc * uc) * uc, fmaf(c, uc, -vc));
-            const float f2 = (-eps) * (fmaf(-b, vc, uc) + a);
+            const float f1 = fmaf(uc, fmaf(-k3, uc * uc, c), -vc);
+            const float f2 = fmaf(eps * b, vc, fmaf(-eps, uc, -(eps * a)));
             un[i * C + j] = fmaf(dt, fmaf(Du, LU, f1), uc);
             vn[i * C + j] = fmaf(dt, fmaf(Dv, LV, f2), vc);
         }

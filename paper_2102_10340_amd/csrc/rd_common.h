@@ -4,8 +4,8 @@
 // rounding order is fixed so that every kernel of this library gives the same
 // bits for the same state, whatever its tiling or time blocking:
 //   sU = (uN + uS) + (uW + uE);   LU = fma(-4, u, sU)      (same for v)
-//   f1 = fma(-k3, (u*u)*u, fma(c, u, -v))                   Eq. (2)
-//   f2 = (-eps) * (fma(-b, v, u) + a)                       Eq. (3)
+//   f1 = fma(u, fma(-k3, u*u, c), -v)                       Eq. (2): c u - k3 u^3 - v
+//   f2 = fma(eps*b, v, fma(-eps, u, -(eps*a)))              Eq. (3): -eps (u - b v + a)
 //   u+ = fma(dt, fma(Du, LU, f1), u);  v+ = fma(dt, fma(Dv, LV, f2), v)
 // The sources are built with -ffp-contract=off (no other fusion) and without
 // denormal flushing, so v_fma_f32 / v_mul_f32 / v_add_f32 round exactly as
@@ -33,8 +33,8 @@ __device__ __forceinline__ void cell_update(const Gene &g, float uc, float vc, f
     const float sV = (vN + vS) + (vW + vE);
     const float LU = __builtin_fmaf(-4.0f, uc, sU);
     const float LV = __builtin_fmaf(-4.0f, vc, sV);
-    const float f1 = __builtin_fmaf(-g.k3, (uc * uc) * uc, __builtin_fmaf(g.c, uc, -vc));
-    const float f2 = (-g.eps) * (__builtin_fmaf(-g.b, vc, uc) + g.a);
+    const float f1 = __builtin_fmaf(uc, __builtin_fmaf(-g.k3, uc * uc, g.c), -vc);
+    const float f2 = __builtin_fmaf(g.eps * g.b, vc, __builtin_fmaf(-g.eps, uc, -(g.eps * g.a)));
     uo = __builtin_fmaf(g.dt, __builtin_fmaf(g.Du, LU, f1), uc);
     vo = __builtin_fmaf(g.dt, __builtin_fmaf(g.Dv, LV, f2), vc);
 }
