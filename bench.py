@@ -30,8 +30,8 @@ R = C = 4096
 T_CHUNK = 10000
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL_UPDATE = 16  # read u, v and write u, v once per explicit step
-FLOPS_PER_CELL_UPDATE = 28  # 7 add + 3 mul + 9 fma of Eq. (1)-(3)
-VALU_OPS_PER_CELL_UPDATE = 19
+FLOPS_PER_CELL_UPDATE = 27  # 6 add + 1 mul + 10 fma of Eq. (1)-(3) in the kernels' order
+VALU_OPS_PER_CELL_UPDATE = 17
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: one non-packed VALU op per lane per clock
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
