@@ -1,8 +1,10 @@
 """Autotuner for the pass shape of the streamed kernels.
 
 For a grid shape and a mode -- "forward" (rdcnn_step), "record"
-(rdcnn_step_record), "adjoint" (rdcnn_adjoint) or "batch" (rdcnn_batch_step
-over a given mix of instance sizes) -- it times candidate settings
+(rdcnn_step_record), "record_even" (rdcnn_step_record_even), "adjoint"
+(rdcnn_adjoint), "adjoint_even" (rdcnn_adjoint_even, the paired passes) or
+"batch" (rdcnn_batch_step over a given mix of instance sizes) -- it times
+candidate settings
 
     depth          time steps per HBM pass
     cols_per_lane  1, 2 or 4 adjacent columns per lane (strip = 64 * cols)
@@ -12,7 +14,8 @@ with HIP events on the current stream and keeps the fastest.  Every setting
 gives bit-identical states (the forward) or the same adjoint up to float32
 summation order, so tuning only changes speed.  Results are cached in a JSON
 file keyed by GPU architecture, mode, size and boundary rule; ``apply`` sets a
-cached choice on a Simulation or Batch.
+cached choice on a Simulation (for plain runs, or for the even recording and
+paired adjoint that gradients use) or a Batch.
 
 The package ships ``tuned.json`` with results measured on an MI355X for the
 benchmark shapes; ``RDCNN_TUNE_CACHE`` names another file.
@@ -31,6 +34,7 @@ from .sim import Simulation
 SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 MAX_DEPTH = {1: 16, 2: 16, 4: 12}
 MAX_ADJ_DEPTH = {1: 8, 2: 8, 4: 6}
+EVEN_DEPTHS = (2, 4, 6, 8)  # even-time recording and paired passes: even depths, <= 2 columns
 # A stable, non-trivial parameter set for timing (speed does not depend on it).
 TUNE_GENE = dict(dt=0.1, a=0.0, b=1.0, eps=-0.1, c=1.0, k3=1.0, Du=0.05, Dv=1.0)
 
@@ -94,6 +98,14 @@ def candidates(mode: str, rows: int, cols: int):
                     continue
                 for seg in (0, 8):
                     out.append((depth, cpl, seg))
+    elif mode in ("record_even", "adjoint_even"):
+        segs = (0, 4, 6, 8, 16, 32) if mode == "record_even" else (0, 4, 5, 6, 8)
+        for cpl in (1, 2):
+            if cpl > 1 and 64 * cpl > 2 * cols:
+                continue
+            for depth in EVEN_DEPTHS:
+                for seg in segs:
+                    out.append((depth, cpl, seg))
     else:
         raise ValueError(mode)
     return out
@@ -132,16 +144,16 @@ def tune(mode: str, rows: int, cols: int, bc: str = "zeroflux", gene=None, budge
     T = _steps_for(rows * cols)
     results = {}
     t_end = time.time() + budget_s
-    if mode == "adjoint":
-        S = min(T, 64)
-        states = torch.empty((S, 2, rows, cols), dtype=torch.float32, device="cuda")
-        sim.step_record(S, states)
+    S = min(T, 64)
+    even = mode in ("record_even", "adjoint_even")
+    if mode in ("record", "record_even", "adjoint", "adjoint_even"):
+        states = torch.empty(((S + 1) // 2 if even else S, 2, rows, cols), dtype=torch.float32,
+                             device="cuda")
+    if mode in ("adjoint", "adjoint_even"):
+        (sim.step_record_even if even else sim.step_record)(S, states)
         adj = torch.randn((2, rows, cols), device="cuda")
         tmp = torch.empty_like(adj)
         dth = torch.zeros(8, dtype=torch.float64, device="cuda")
-    elif mode == "record":
-        S = min(T, 64)
-        states = torch.empty((S, 2, rows, cols), dtype=torch.float32, device="cuda")
     for cand in candidates(mode, rows, cols):
         if time.time() > t_end:
             break
@@ -150,13 +162,15 @@ def tune(mode: str, rows: int, cols: int, bc: str = "zeroflux", gene=None, budge
             sim.set_kernel(2, depth, cpl, seg)
             t = run(lambda: sim.step(T))
             rate = rows * cols * T / t / 1e9
-        elif mode == "record":
+        elif mode in ("record", "record_even"):
             sim.set_kernel(2, depth, cpl, seg)
-            t = run(lambda: sim.step_record(S, states))
+            rec = sim.step_record_even if even else sim.step_record
+            t = run(lambda: rec(S, states))
             rate = rows * cols * S / t / 1e9
         else:
             sim.set_adjoint_kernel(depth, cpl, seg)
-            t = run(lambda: sim.adjoint(states, S, adj, tmp, dth))
+            adjf = sim.adjoint_even if even else sim.adjoint
+            t = run(lambda: adjf(states, S, adj, tmp, dth))
             rate = rows * cols * S / t / 1e9
         results[cand] = rate
         if verbose:
@@ -202,9 +216,11 @@ def lookup(k: str, path: str = None):
     return None if e is None else (e["depth"], e["cols_per_lane"], e["seg_rows"])
 
 
-def apply(obj, path: str = None) -> bool:
-    """Set the cached settings (if any) on a Simulation (forward and adjoint) or
-    a Batch; returns True if something was applied."""
+def apply(obj, path: str = None, grad: bool = False) -> bool:
+    """Set the cached settings (if any) on a Simulation or a Batch; returns True
+    if something was applied.  For a Simulation, grad=False takes the "forward"
+    and "adjoint" entries, grad=True the "record_even" and "adjoint_even" ones
+    (what a gradient run uses)."""
     from .batch import Batch
     done = False
     if isinstance(obj, Batch):
@@ -213,11 +229,11 @@ def apply(obj, path: str = None) -> bool:
             obj.set_kernel(*cfg)
             done = True
         return done
-    cfg = lookup(key("forward", obj.rows, obj.cols, obj.bc), path)
+    cfg = lookup(key("record_even" if grad else "forward", obj.rows, obj.cols, obj.bc), path)
     if cfg:
         obj.set_kernel(2, *cfg)
         done = True
-    cfg = lookup(key("adjoint", obj.rows, obj.cols, obj.bc), path)
+    cfg = lookup(key("adjoint_even" if grad else "adjoint", obj.rows, obj.cols, obj.bc), path)
     if cfg:
         obj.set_adjoint_kernel(*cfg)
         done = True
@@ -230,7 +246,8 @@ if __name__ == "__main__":
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     ap = argparse.ArgumentParser(description="tune pass shapes and update the cache")
     ap.add_argument("--mode", default="forward",
-                    choices=["forward", "record", "adjoint", "batch-sweep"])
+                    choices=["forward", "record", "record_even", "adjoint", "adjoint_even",
+                             "batch-sweep"])
     ap.add_argument("--size", type=int, nargs="+", default=[4096, 1024, 256])
     ap.add_argument("--bc", default="zeroflux")
     ap.add_argument("--budget", type=float, default=60.0)

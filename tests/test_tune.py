@@ -8,11 +8,13 @@ import pytest
 
 def test_candidates_respect_depth_limits():
     from paper_2102_10340_amd import tune
-    for mode in ("forward", "record", "adjoint", "batch"):
+    for mode in ("forward", "record", "adjoint", "batch", "record_even", "adjoint_even"):
         c = tune.candidates(mode, 1024, 1024)
         assert c and len(set(c)) == len(c)
         lim = tune.MAX_ADJ_DEPTH if mode == "adjoint" else tune.MAX_DEPTH
         assert all(1 <= d <= lim[cpl] and cpl in (1, 2, 4) and s >= 0 for d, cpl, s in c)
+        if mode.endswith("_even"):  # paired passes and even recording: even depths <= 8, <= 2 columns
+            assert all(d % 2 == 0 and d <= 8 and cpl <= 2 for d, cpl, _ in c)
     # narrow grids do not try strips much wider than themselves
     assert all(cpl == 1 for _, cpl, _ in tune.candidates("forward", 64, 16))
 
@@ -55,3 +57,32 @@ def test_tuned_settings_stay_bitwise(tmp_path, monkeypatch):
     sim.close()
     ou, ov = oracle.run(*oracle.init_state(x, 1.0), W.PLAIN_GENE, "zeroflux", 30, "f32")
     assert np.array_equal(u, ou) and np.array_equal(v, ov)
+
+
+@pytest.mark.gpu
+def test_tuned_gradient_settings_keep_the_adjoint(tmp_path, monkeypatch):
+    """Tuning the even recording and the paired adjoint, then applying them with
+    grad=True, leaves dJ/ds bit-identical to the default settings (the per-cell
+    arithmetic does not depend on the pass shape)."""
+    import torch
+    import workloads as W
+    from paper_2102_10340_amd import Simulation, tune
+    monkeypatch.setenv("RDCNN_TUNE_CACHE", str(tmp_path / "t.json"))
+    R, C, T = 96, 200, 21
+    for mode in ("record_even", "adjoint_even"):
+        best, res = tune.tune(mode, R, C, "zeroflux", budget_s=3.0)
+        assert best in res and all(v > 0 for v in res.values())
+    x = torch.from_numpy(W.uniform_x(R, C, 5)).cuda()
+    w = torch.from_numpy(np.random.default_rng(5).standard_normal((2, R, C)).astype(np.float32)).cuda()
+    out = []
+    for tuned in (False, True):
+        sim = Simulation(x, W.PLAIN_GENE, "zeroflux")
+        if tuned:
+            assert tune.apply(sim, grad=True)
+        st = torch.empty(((T + 1) // 2, 2, R, C), device="cuda")
+        sim.step_record_even(T, st)
+        adj = w.clone()
+        sim.adjoint_even(st, T, adj, torch.empty_like(adj), torch.zeros(8, dtype=torch.float64, device="cuda"))
+        out.append((st.clone(), adj))
+        sim.close()
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
