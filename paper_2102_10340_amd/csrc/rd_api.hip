@@ -267,6 +267,31 @@ int run_steps(rdcnn_sim *h, long long n, float *rec, bool rec_even = false)
             depth = (int)cap;
         }
     }
+    if (rec && rec_even && kind == 2 && depth >= 2 && n > 0) {
+        // Every pass but the last writes its output straight into the
+        // trajectory slot of the (even) time it ends at; the next pass reads
+        // its input from there and records from level 2 on, so each recorded
+        // state is written once.  No pass reads a slot it writes.  The last
+        // pass writes the handle's other buffer.
+        const size_t state = 2 * (size_t)h->R * h->C;
+        const float *in = h->buf[h->cur];
+        while (n > 0) {
+            const int k = (int)(n < depth ? n : depth);
+            float *out = n == k ? h->buf[1 - h->cur] : rec + (size_t)((q + k) / 2) * state;
+            rd::StreamGeom geom;
+            if (!rd::stream_geometry(h->R, h->C, cpl, k, seg, &geom))
+                return fail(RDCNN_EINVAL, "rdcnn_step: cannot tile %dx%d with cpl=%d depth=%d",
+                            h->R, h->C, cpl, k);
+            hipError_t e = rd::launch_stream(in, out, h->R, h->C, h->bc, h->g, geom, h->stream,
+                                             rec, q / 2, true, q > 0);
+            if (e != hipSuccess) return hip_fail(e, "rdcnn_step: kernel launch");
+            in = out;
+            n -= k;
+            q += k;
+        }
+        h->cur = 1 - h->cur;
+        return RDCNN_OK;
+    }
     while (n > 0) {
         hipError_t e;
         const float *in = h->buf[h->cur];

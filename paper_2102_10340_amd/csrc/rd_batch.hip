@@ -34,7 +34,7 @@ struct BatchArgs {
 };
 
 // REC: 0 plain steps; 1 record every level; 2 record the even levels (passes
-// start at even times).
+// start at even times); 3 as 2 without level 0 (the input is that state).
 template <int CPL, int K, int REC>
 __global__ __launch_bounds__(64) void batch_step_kernel(BatchArgs B)
 {
@@ -210,10 +210,15 @@ constexpr BatchFn pick(int k, std::integer_sequence<int, Ks...>)
 
 hipError_t launch_batch(const BatchTile *tiles, const BatchInst *insts, int ntiles,
                         const float *in, float *out, int bc, int cpl, int depth, hipStream_t s,
-                        float *rec, unsigned rec_stride, bool rec_even)
+                        float *rec, unsigned rec_stride, bool rec_even, bool skip_level0)
 {
     BatchFn f = nullptr;
-    if (rec && rec_even) {  // recording passes: cpl 1 or 2, depth <= 8
+    if (rec && rec_even && skip_level0) {  // recording passes: cpl 1 or 2, depth <= 8
+        if (cpl == 2)
+            f = pick<2, 3>(depth, std::make_integer_sequence<int, 8>{});
+        else if (cpl == 1)
+            f = pick<1, 3>(depth, std::make_integer_sequence<int, 8>{});
+    } else if (rec && rec_even) {
         if (cpl == 2)
             f = pick<2, 2>(depth, std::make_integer_sequence<int, 8>{});
         else if (cpl == 1)
@@ -738,6 +743,29 @@ int batch_record(rdcnn_batch *b, long long T, float *traj, bool even, const char
         b->rec_cpl = cpl;
     }
     long long q = 0;
+    if (even && depth >= 2) {
+        // As for a single grid: every pass but the last writes its output into
+        // the trajectory slot of the even time it ends at, and the next pass
+        // reads it there and records from level 2 on (each recorded state is
+        // written once); the last pass writes the batch's other buffer.
+        const float *in = b->buf[b->cur];
+        while (T > 0) {
+            const int k = (int)(T < depth ? T : depth);
+            const TileTable *t = nullptr;
+            int rc = table_in(b, b->rec_tables, cpl, k, seg, false, &t);
+            if (rc != RDCNN_OK) return rc;
+            float *out = T == k ? b->buf[1 - b->cur] : traj + (q + k) / 2 * b->total;
+            hipError_t e = rd::launch_batch(t->dev, b->insts_dev, t->ntiles, in, out, b->bc, cpl,
+                                            k, b->stream, traj + q / 2 * b->total,
+                                            (unsigned)(4 * b->total), true, q > 0);
+            if (e != hipSuccess) return bfail(RDCNN_EHIP, "%s: %s", who, hipGetErrorString(e));
+            in = out;
+            q += k;
+            T -= k;
+        }
+        b->cur = 1 - b->cur;
+        return RDCNN_OK;
+    }
     while (T > 0) {
         const int k = (int)(T < depth ? T : depth);
         const TileTable *t = nullptr;

@@ -142,7 +142,7 @@ constexpr StreamFn pick(int k, std::integer_sequence<int, Ks...>)
 template <int REC>
 StreamFn pick_stream(int cpl, int depth)
 {
-    if (REC == 2) {  // even-state recording: one or two columns per lane, depth <= 8
+    if (REC >= 2) {  // even-state recording: one or two columns per lane, depth <= 8
         if (cpl == 2) return pick<2, REC>(depth, std::make_integer_sequence<int, 8>{});
         if (cpl == 1) return pick<1, REC>(depth, std::make_integer_sequence<int, 8>{});
         return nullptr;
@@ -173,11 +173,12 @@ TileArgs tile_args(int R, int C, int bc, const StreamGeom &geom)
 
 hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, const Gene &g,
                          const StreamGeom &geom, hipStream_t s, float *rec, long long rec_q0,
-                         bool rec_even)
+                         bool rec_even, bool skip_level0)
 {
     StreamFn f = !rec ? pick_stream<0>(geom.cpl, geom.depth)
-                      : rec_even ? pick_stream<2>(geom.cpl, geom.depth)
-                                 : pick_stream<1>(geom.cpl, geom.depth);
+                 : !rec_even ? pick_stream<1>(geom.cpl, geom.depth)
+                 : skip_level0 ? pick_stream<3>(geom.cpl, geom.depth)
+                               : pick_stream<2>(geom.cpl, geom.depth);
     if (!f) return hipErrorInvalidValue;
     StreamArgs a;
     a.t = tile_args(R, C, bc, geom);

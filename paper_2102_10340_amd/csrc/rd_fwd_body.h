@@ -39,7 +39,9 @@ using StreamArgs = StreamArgsT<ModelFHN>;
 // boundary mapping (true for all but the first and last segments of a strip).
 // REC: 0 no recording; 1 record every level (states q0 .. q0+K-1 of the pass);
 // 2 record the even levels only (the pass starts at an even time q0; level j
-// goes to recorded state j/2), for the reverse pass that rebuilds odd states.
+// goes to recorded state j/2), for the reverse pass that rebuilds odd states;
+// 3 as 2 but without level 0, for a pass whose input already is that
+// recorded state (the previous pass wrote its output there).
 template <class M, int CPL, int K, int REC, bool FAST, bool ROWS_IN>
 __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<CPL> &t)
 {
@@ -49,7 +51,7 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
     const Buf iu(A.in, pbytes), iv(A.in + (size_t)R * C, pbytes);
     const Buf ou(A.out, pbytes), ov(A.out + (size_t)R * C, pbytes);
     // Recorded states, u plane then v plane each: state j at byte j*rec_stride.
-    constexpr int kRecLast = REC == 2 ? (K - 1) / 2 : K - 1;  // last recorded state of a pass
+    constexpr int kRecLast = REC >= 2 ? (K - 1) / 2 : K - 1;  // last recorded state of a pass
     const unsigned rstride = A.rec_stride;
     const Buf rb(REC ? A.rec : A.in, REC ? (unsigned)kRecLast * rstride + 2u * pbytes : 0u);
     const typename M::Params g = A.g;
@@ -161,7 +163,7 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
                 const unsigned ro = roff(rbase + it + kFwdFetch);
                 load_row<CPL, FAST>(iu, ro, t, l0u[(S6 + kFwdFetch) % 6]);
                 load_row<CPL, FAST>(iv, ro, t, l0v[(S6 + kFwdFetch) % 6]);
-                if (REC) {
+                if (REC == 1 || REC == 2) {
                     const int m = rbase + it;  // level-0 row it
                     if (m >= y0 && m < y1) {
                         const unsigned o = 4u * (unsigned)m * C;
@@ -174,7 +176,7 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
                 it < n_real) {
                 const int m = rbase + it - j - 1;  // level-(j+1) row just made
                 if (m >= y0 && m < y1) {
-                    const unsigned o = (unsigned)(REC == 2 ? (j + 1) / 2 : j + 1) * rstride +
+                    const unsigned o = (unsigned)(REC >= 2 ? (j + 1) / 2 : j + 1) * rstride +
                                        4u * (unsigned)m * C;
                     store_row<CPL, FAST>(rb, o, C, t, bu[j + 1][sl.cs]);
                     store_row<CPL, FAST>(rb, o + pbytes, C, t, bv[j + 1][sl.cs]);

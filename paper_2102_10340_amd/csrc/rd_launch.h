@@ -61,10 +61,11 @@ hipError_t launch_naive(const float *in, float *out, int R, int C, int bc, const
 // not null, the states the pass steps from (levels 0..depth-1) are also written
 // to rec + (rec_q0 + j) * 2*R*C; with rec_even only the even levels, level j to
 // rec + (rec_q0 + j/2) * 2*R*C (the pass must start at an even time; cpl 1 or
-// 2, depth <= 8).
+// 2, depth <= 8), and with skip_level0 too the even levels from 2 on (`in` is
+// already recorded state rec_q0).
 hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, const Gene &g,
                          const StreamGeom &geom, hipStream_t s, float *rec = nullptr,
-                         long long rec_q0 = 0, bool rec_even = false);
+                         long long rec_q0 = 0, bool rec_even = false, bool skip_level0 = false);
 
 // Cell models other than FitzHugh-Nagumo on the same streamed kernel
 // (rd_models.h).  Their passes take depth 1, 2, 4 or 8 and cols_per_lane 1 or 2.
@@ -123,7 +124,8 @@ struct BatchTile {
 // to rec + (j/2) * rec_stride bytes (the pass starts at an even time).
 hipError_t launch_batch(const BatchTile *tiles, const BatchInst *insts, int ntiles,
                         const float *in, float *out, int bc, int cpl, int depth, hipStream_t s,
-                        float *rec = nullptr, unsigned rec_stride = 0, bool rec_even = false);
+                        float *rec = nullptr, unsigned rec_stride = 0, bool rec_even = false,
+                        bool skip_level0 = false);
 
 // Batched reverse pass: `depth` (1, 2, 4 or 8) reverse steps for every tile,
 // cpl 1 or 2; states = packed state q_top-depth+1, state_stride bytes apart.
