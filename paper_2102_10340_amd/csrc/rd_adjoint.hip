@@ -47,17 +47,27 @@ struct AdjArgs {
 // (1 for the tile's output cells, 0 for halo cells; FAST tiles weight a lane's
 // sums once at the end instead).  LAMS: also the three lam-weighted products
 // only dJ/ddt, dJ/dc and dJ/dk3 need (S_LU, S_LU3, S_LV).
+// The dt-scaled constants of the reverse step, formed once per wavefront:
+//   lam = lam' + (dt c - 3 dt k3 u^2) lam' + dt Du Lap(lam') - dt eps mu'
+//   mu  = mu' + dt Dv Lap(mu') + dt eps b mu' - dt lam'
+struct AdjConst {
+    float dc, d3k, dDu, deps, dDv, depsb, dt;
+    __device__ __forceinline__ explicit AdjConst(const Gene &g)
+        : dc(g.dt * g.c), d3k(g.dt * (3.0f * g.k3)), dDu(g.dt * g.Du), deps(g.dt * g.eps),
+          dDv(g.dt * g.Dv), depsb(g.dt * (g.eps * g.b)), dt(g.dt)
+    {
+    }
+};
+
 template <bool FAST, bool LAMS>
-__device__ __forceinline__ void adj_cell(const Gene &g, float c3k, float epsb, float l, float mu,
-                                         float Ll, float Lm, float u, float v, int count, float we,
-                                         float &lo, float &mo, float (&acc)[NSUM])
+__device__ __forceinline__ void adj_cell(const AdjConst &k, float l, float mu, float Ll, float Lm,
+                                         float u, float v, int count, float we, float &lo,
+                                         float &mo, float (&acc)[NSUM])
 {
     const float u2 = u * u;
-    const float gl = __builtin_fmaf(-c3k, u2, g.c) * l;
-    const float rl_ = __builtin_fmaf(-g.eps, mu, __builtin_fmaf(g.Du, Ll, gl));
-    lo = __builtin_fmaf(g.dt, rl_, l);
-    const float rm_ = __builtin_fmaf(g.Dv, Lm, __builtin_fmaf(epsb, mu, -l));
-    mo = __builtin_fmaf(g.dt, rm_, mu);
+    const float gl = __builtin_fmaf(__builtin_fmaf(-k.d3k, u2, k.dc), l, l);
+    lo = __builtin_fmaf(k.dDu, Ll, __builtin_fmaf(-k.deps, mu, gl));
+    mo = __builtin_fmaf(k.dDv, Lm, __builtin_fmaf(k.depsb, mu, __builtin_fmaf(-k.dt, l, mu)));
     if (count) {  // halo cells enter with weight 0
         const float uw = FAST ? u : we * u, vw = FAST ? v : we * v;
         acc[S_LLU] = __builtin_fmaf(Ll, uw, acc[S_LLU]);
@@ -106,8 +116,7 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &
     const unsigned sstride = A.state_stride;
     const Buf sb(A.states, (unsigned)(KB - 1) * sstride + 2u * pbytes);
     const Gene g = A.g;
-    const float c3k = 3.0f * g.k3;
-    const float epsb = g.eps * g.b;
+    const AdjConst kc(g);
     const int y0 = t.y0, y1 = t.y1;
     const int rbase = y0 - KB;
     const int n_real = y1 - y0 + 2 * KB;
@@ -176,8 +185,8 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &
                     const float sm_ = sw ? mE + mW : mW + mE;
                     const float Ll = __builtin_fmaf(-4.0f, l, (bl[i][sl.ps][e] + bl[i][sl.ns][e]) + sl_);
                     const float Lm = __builtin_fmaf(-4.0f, mu, (bm[i][sl.ps][e] + bm[i][sl.ns][e]) + sm_);
-                    adj_cell<FAST, LAMS>(g, c3k, epsb, l, mu, Ll, Lm, su[i][sl.cs][e],
-                                         sv[i][sl.cs][e], count, w[e], dl[e], dm[e], acc);
+                    adj_cell<FAST, LAMS>(kc, l, mu, Ll, Lm, su[i][sl.cs][e], sv[i][sl.cs][e],
+                                         count, w[e], dl[e], dm[e], acc);
                 }
             }
             // Loads in the order they are needed (vmcnt retires in issue
@@ -263,8 +272,7 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
     const unsigned sstride = A.state_stride;  // E_p at (P-1-p) * sstride
     const Buf sb(A.states, (unsigned)(P - 1) * sstride + 2u * pbytes);
     const Gene g = A.g;
-    const float c3k = 3.0f * g.k3;
-    const float epsb = g.eps * g.b;
+    const AdjConst kc(g);
     const int y0 = t.y0, y1 = t.y1;
     const int rbase = y0 - KB;
     const int n_real = y1 - y0 + 2 * KB;
@@ -369,8 +377,8 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
                     const float sm_ = sw ? mE + mW : mW + mE;
                     const float Ll = __builtin_fmaf(-4.0f, lC[e], (lN[e] + lS[e]) + sl_);
                     const float Lm = __builtin_fmaf(-4.0f, mC[e], (mN[e] + mS[e]) + sm_);
-                    adj_cell<FAST, LAMS>(g, c3k, epsb, lC[e], mC[e], Ll, Lm, u[e], v[e], count,
-                                         w[e], dl[e], dm[e], acc);
+                    adj_cell<FAST, LAMS>(kc, lC[e], mC[e], Ll, Lm, u[e], v[e], count, w[e],
+                                         dl[e], dm[e], acc);
                 }
             }
             // Fetches, in the order they are needed: the level-0 row DL
