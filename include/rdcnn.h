@@ -206,8 +206,10 @@ int rdcnn_adjoint(rdcnn_t h, const float *states_dev, long long S, float *adj_de
  * states_dev[i] for 2i < T, i.e. (T+1)/2 states of 2*rows*cols floats each
  * (half the memory and half the writes).  Passes run 8 steps (or the even
  * depth set with rdcnn_set_kernel; at most 8, one or two columns per lane).
- * These are the states rdcnn_adjoint_even reads.  Asynchronous.
- * Errors: RDCNN_EINVAL, RDCNN_EHIP.
+ * The passes also read their input from, and write their output to,
+ * states_dev (each recorded state is written once), so states_dev must not
+ * overlap the handle's state buffers.  These are the states rdcnn_adjoint_even
+ * reads.  Asynchronous.  Errors: RDCNN_EINVAL, RDCNN_EHIP.
  */
 int rdcnn_step_record_even(rdcnn_t h, long long T, float *states_dev);
 
@@ -364,7 +366,9 @@ int rdcnn_batch_adjoint(rdcnn_batch_t b, const float *traj, long long S, float *
  * rdcnn_batch_step_record_even -- rdcnn_batch_step_record keeping only the
  * states of even times: packed state 2i goes to traj + i * buf_floats for
  * 2i < T ((T+1)/2 states; half the memory and writes).  Passes take an even
- * depth (at most 8).  The trajectory rdcnn_batch_adjoint_even reads.
+ * depth (at most 8) and read their input from, and write their output to, traj
+ * (each recorded state is written once), so traj must not overlap the batch's
+ * state buffers.  The trajectory rdcnn_batch_adjoint_even reads.
  * Errors: as rdcnn_batch_step_record.
  */
 int rdcnn_batch_step_record_even(rdcnn_batch_t b, long long T, float *traj);

@@ -480,6 +480,19 @@ int rdcnn_step_record_even(rdcnn_t h, long long T, float *states_dev)
     if (T < 0) return fail(RDCNN_EINVAL, "rdcnn_step_record_even: T = %lld < 0", T);
     if (T > 0 && !states_dev)
         return fail(RDCNN_EINVAL, "rdcnn_step_record_even: NULL states buffer");
+    if (T > 0) {
+        // the passes read their input from the trajectory: it must not overlap
+        // the handle's state buffers
+        const size_t state = 2 * (size_t)h->R * h->C;
+        const char *t0 = (const char *)states_dev;
+        const char *t1 = t0 + sizeof(float) * state * (size_t)((T + 1) / 2);
+        for (float *b : h->buf) {
+            const char *b0 = (const char *)b, *b1 = b0 + sizeof(float) * state;
+            if (t0 < b1 && b0 < t1)
+                return fail(RDCNN_EINVAL, "rdcnn_step_record_even: states buffer overlaps a "
+                                          "state buffer of the handle");
+        }
+    }
     return run_steps(h, T, states_dev, true);
 }
 

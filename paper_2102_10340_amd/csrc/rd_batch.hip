@@ -718,6 +718,18 @@ int batch_record(rdcnn_batch *b, long long T, float *traj, bool even, const char
     if (T < 0) return bfail(RDCNN_EINVAL, "%s: T = %lld < 0", who, T);
     if (T == 0) return RDCNN_OK;
     if (!traj) return bfail(RDCNN_EINVAL, "%s: NULL trajectory", who);
+    {
+        // the recorded states (and, for even recording, the passes' inputs)
+        // must not overlap the batch's state buffers
+        const long long n = even ? (T + 1) / 2 : T;
+        const char *t0 = (const char *)traj, *t1 = t0 + sizeof(float) * b->total * n;
+        for (float *p : b->buf) {
+            const char *b0 = (const char *)p, *b1 = b0 + sizeof(float) * b->total;
+            if (t0 < b1 && b0 < t1)
+                return bfail(RDCNN_EINVAL, "%s: trajectory overlaps a state buffer of the batch",
+                             who);
+        }
+    }
     int cpl, depth, seg;
     batch_config(b, &cpl, &depth, &seg);
     if (cpl > 2) cpl = 2;  // recording passes exist for 1 or 2 columns per lane

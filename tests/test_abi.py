@@ -99,6 +99,10 @@ def test_null_handle_calls_fail_cleanly(L):
     assert L.lib.rdcnn_batch_stats(None, None, None, 0.0, 0.0, 0x1000) == L.EINVAL
     assert L.lib.rdcnn_batch_use_lds(None, 1) == L.EINVAL
     assert L.lib.rdcnn_batch_lds_instances(None, None) == L.EINVAL
+    assert L.lib.rdcnn_step_record_even(None, 4, 0x1000) == L.EINVAL
+    assert L.lib.rdcnn_adjoint_even(None, 0x1000, 4, 0x2000, 0x3000, 0x4000) == L.EINVAL
+    assert L.lib.rdcnn_batch_step_record_even(None, 4, 0x1000) == L.EINVAL
+    assert L.lib.rdcnn_batch_adjoint_even(None, 0x1000, 4, 0x2000, 0x3000, 0xFF, 0x4000) == L.EINVAL
     assert "NULL" in L.last_error()
 
 

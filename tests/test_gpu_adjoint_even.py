@@ -123,11 +123,13 @@ def test_adjoint_even_matches_oracle(bc):
 
 
 def test_even_entry_points_reject_bad_buffers():
-    from paper_2102_10340_amd import RDCNNError, Simulation
+    from paper_2102_10340_amd import RDCNNError, Simulation, _lib
     sim = Simulation(torch.zeros((8, 8), device="cuda"), W.PLAIN_GENE, "zeroflux")
     st = torch.zeros((4, 2, 8, 8), device="cuda")
     with pytest.raises(ValueError):
         sim.step_record_even(9, st)  # needs 5 states
+    with pytest.raises(RDCNNError):  # the trajectory may not overlap the state buffers
+        _lib.check(_lib.lib.rdcnn_step_record_even(sim._h, 2, sim.buf[1].data_ptr()))
     adj = torch.zeros((2, 8, 8), device="cuda")
     dth = torch.zeros(8, dtype=torch.float64, device="cuda")
     with pytest.raises(RDCNNError):
@@ -220,4 +222,7 @@ def test_batch_adjoint_even_rejects_depth_one():
     dth = torch.zeros((1, 8), dtype=torch.float64, device="cuda")
     with pytest.raises(RDCNNError):
         b.adjoint_even(traj, 4, adj, torch.empty_like(adj), 0xFF, dth)
+    from paper_2102_10340_amd import _lib
+    with pytest.raises(RDCNNError):  # the trajectory may not overlap the state buffers
+        _lib.check(_lib.lib.rdcnn_batch_step_record_even(b._h, 2, b.buf[0].data_ptr()))
     b.close()
