@@ -41,7 +41,7 @@ def _sim(x, g, bc, kernel=None):
                          ids=lambda k: "auto" if k is None else "k%d_d%d_c%d_h%d" % k)
 @pytest.mark.parametrize("bc", BCS)
 @pytest.mark.parametrize("shape", [(1, 1), (5, 9), (40, 300), (129, 257)], ids=lambda s: "%dx%d" % s)
-@pytest.mark.parametrize("T", [1, 18, 23])
+@pytest.mark.parametrize("T", [1, 9, 17, 18, 23])
 def test_even_recording_bitwise(shape, bc, kernel, T):
     R, C = shape
     x = W.uniform_x(R, C, 7 * R + C)
@@ -153,7 +153,7 @@ def _genes(n, seed):
 @pytest.mark.parametrize("kernel", [None, (1, 1, 0), (5, 2, 7)],
                          ids=lambda k: "auto" if k is None else "d%d_c%d_h%d" % k)
 @pytest.mark.parametrize("bc", BCS)
-@pytest.mark.parametrize("T", [1, 16, 21])
+@pytest.mark.parametrize("T", [1, 9, 16, 17, 21])
 def test_batch_even_recording_bitwise(bc, kernel, T):
     from paper_2102_10340_amd import Batch
     xs = [W.uniform_x(R, C, 40 + i) for i, (R, C) in enumerate(BATCH_SHAPES)]
