@@ -223,3 +223,27 @@ def test_shared_parameters_over_many_images():
     scale = max(abs(v) for v in ref.values())
     for i, k in enumerate(KEYS):
         assert abs(theta.grad[i].item() - ref[k]) <= 1e-3 * max(abs(ref[k]), 1e-3 * scale), k
+
+
+def test_full_size_stationary_identities():
+    """The differentiation workload at full size (1024^2, T = 2000, MSE to the
+    stripe target, autograd through the even-time trajectory and the paired
+    passes).  The plain workload settles, and at a stationary state the fixed
+    point depends on (eps, Dv) only through Dv / eps and not on dt, so
+    eps dL/deps + Dv dL/dDv = 0 and dL/ddt = 0 (the CPU oracle meets both to
+    1e-10 on a float64 trajectory).  The GPU sums in float32 per pass; measured,
+    both hold to ~2e-7 of eps dL/deps, and the bar is 1e-5."""
+    from paper_2102_10340_amd import simulate
+    N, T = 1024, 2000
+    g = W.PLAIN_GENE
+    x = torch.from_numpy(W.uniform_x(N, N, 0)).cuda()
+    target = torch.from_numpy(W.stripe_target(N, N, 0)).cuda()
+    theta = torch.tensor([g[k] for k in KEYS], dtype=torch.float64, requires_grad=True)
+    u, _ = simulate(x.clone().requires_grad_(True), theta, T, "zeroflux")
+    ((u - target) ** 2).mean().backward()
+    d = dict(zip(KEYS, theta.grad.tolist()))
+    se, sd, st = g["eps"] * d["eps"], g["Dv"] * d["Dv"], g["dt"] * d["dt"]
+    print(f"eps*dL/deps {se:.6e}  Dv*dL/dDv {sd:.6e}  dt*dL/ddt {st:.3e}", flush=True)
+    assert abs(se) > 1e-3
+    assert abs(se + sd) <= 1e-5 * abs(se), (se, sd)
+    assert abs(st) <= 1e-5 * abs(se), st

@@ -305,3 +305,27 @@ def test_reverse_pass_zero_steps():
                                     "periodic", 0, wu, wv)
     assert np.array_equal(lam, wu) and np.array_equal(mu, wv)
     assert all(val == 0.0 for val in dp.values())
+
+
+@pytest.mark.parametrize("R", [64, 128])
+def test_adjoint_stationary_scale_invariance(R):
+    """Closed-form identities of the reverse pass at a stationary state.  With
+    a = 0, b = 1 the Euler fixed point solves f1 + Du Lap u = 0 and
+    -eps (u - v) + Dv Lap v = 0 (Eq. (1)-(3)): it depends on (eps, Dv) only
+    through Dv / eps and not on dt.  Once the plain workload has settled
+    (T = 2000), a loss of the final state therefore has
+    eps dL/deps + Dv dL/dDv = 0 and dL/ddt = 0.  A wrong sign or a dropped term
+    in any of these three gradients, or in the mu recursion, breaks them."""
+    x = W.uniform_x(R, R, 0)
+    tgt = W.stripe_target(R, R, 0)
+    g = W.PLAIN_GENE
+    T = 2000
+    u, _ = oracle.run(x, x, g, "zeroflux", T, "f64")
+    u_prev, _ = oracle.run(x, x, g, "zeroflux", T - 100, "f64")
+    assert np.array_equal(u, u_prev), "the state has settled"
+    lam = 2.0 * (u - tgt) / u.size
+    _, _, dp, _, _ = oracle.grad(x, x, g, "zeroflux", T, lam, np.zeros_like(lam), traj="f64")
+    se, sd = g["eps"] * dp["eps"], g["Dv"] * dp["Dv"]
+    assert abs(se) > 1e-3
+    assert abs(se + sd) <= 1e-10 * abs(se)
+    assert abs(g["dt"] * dp["dt"]) <= 1e-10 * abs(se)
