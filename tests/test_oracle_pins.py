@@ -329,3 +329,52 @@ def test_adjoint_stationary_scale_invariance(R):
     assert abs(se) > 1e-3
     assert abs(se + sd) <= 1e-10 * abs(se)
     assert abs(g["dt"] * dp["dt"]) <= 1e-10 * abs(se)
+
+
+def _complex_run(u, v, g, bc, T):
+    """T Euler steps of Eq. (1)-(3) in complex128 (test-side, for complex-step
+    derivatives); its real part is checked against the oracle's float64 run."""
+    def nb(q):
+        if bc == "periodic":
+            return np.roll(q, 1, 0), np.roll(q, -1, 0), np.roll(q, 1, 1), np.roll(q, -1, 1)
+        p = np.pad(q, 1, mode="edge")
+        return p[:-2, 1:-1], p[2:, 1:-1], p[1:-1, :-2], p[1:-1, 2:]
+    for _ in range(T):
+        uN, uS, uW, uE = nb(u)
+        vN, vS, vW, vE = nb(v)
+        lu = uN + uS + uW + uE - 4 * u
+        lv = vN + vS + vW + vE - 4 * v
+        f1 = g["c"] * u - g["k3"] * u ** 3 - v
+        f2 = -g["eps"] * (u - g["b"] * v + g["a"])
+        u, v = u + g["dt"] * (f1 + g["Du"] * lu), v + g["dt"] * (f2 + g["Dv"] * lv)
+    return u, v
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_reverse_pass_matches_complex_step(bc):
+    """Every dJ/dp and a directional dJ/ds_0 from the reverse pass against
+    complex-step derivatives (the step is a polynomial, so Im J(p + i h) / h with
+    h = 1e-30 is exact to rounding, with no cancellation), to 1e-10."""
+    R, C, T = 12, 9, 40
+    g = W.gene(W.PAPER_DEFAULT_GENE, k3=0.45, Du=0.08, Dv=0.6)
+    rng = np.random.default_rng(11)
+    u0, v0 = rng.uniform(-1, 1, (R, C)), rng.uniform(-1, 1, (R, C))
+    wu, wv = _loss_and_seed(R, C, 12)
+    lam0, mu0, dp, _, _ = oracle.grad(u0, v0, g, bc, T, wu, wv, traj="f64")
+    ur, vr = _complex_run(u0.astype(complex), v0.astype(complex), g, bc, T)
+    uo, vo = oracle.run(u0, v0, g, bc, T, "f64")
+    assert np.abs(ur.real - uo).max() < 1e-13 and np.abs(vr.real - vo).max() < 1e-13
+    h = 1e-30
+
+    def J(u, v):
+        return (wu * u).sum() + (wv * v).sum()
+
+    for k in oracle.PARAM_ORDER:
+        gk = {q: complex(val) for q, val in g.items()}
+        gk[k] += 1j * h
+        cs = J(*_complex_run(u0.astype(complex), v0.astype(complex), gk, bc, T)).imag / h
+        assert abs(dp[k] - cs) <= 1e-10 * max(1.0, abs(cs)), (k, dp[k], cs)
+    du, dv = rng.standard_normal((R, C)), rng.standard_normal((R, C))
+    cs = J(*_complex_run(u0 + 1j * h * du, v0 + 1j * h * dv, g, bc, T)).imag / h
+    an = float((lam0 * du).sum() + (mu0 * dv).sum())
+    assert abs(an - cs) <= 1e-10 * max(1.0, abs(cs))
