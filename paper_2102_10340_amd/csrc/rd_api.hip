@@ -346,6 +346,21 @@ void adj_auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows)
     *seg_rows = (int)seg;
 }
 
+// Default shape of the paired reverse passes: three pairs per pass, one column
+// per lane, and segments for ~2560 wavefronts led an interleaved sweep on
+// 1024^2 (4 % over the plain reverse pass's shape of 4 steps and ~4608).
+void adj_even_auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows)
+{
+    *cpl = 1;
+    *depth = 6;
+    const long long nstrips = (h->C + (64 - 2 * 6) - 1) / (64 - 2 * 6);
+    long long want = 2560 / nstrips;
+    if (want < 1) want = 1;
+    long long seg = (h->R + want - 1) / want;
+    if (seg < 4) seg = 4;
+    *seg_rows = (int)seg;
+}
+
 int check_grid(const char *who, int rows, int cols, int bc, const float *buf0, const float *buf1)
 {
     if (rows < 1 || cols < 1) return fail(RDCNN_EINVAL, "%s: grid %dx%d", who, rows, cols);
@@ -586,7 +601,7 @@ int rdcnn_adjoint_even(rdcnn_t h, const float *states_dev, long long S, float *a
     if (adj_dev == adj_tmp_dev) return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: adj buffers alias");
     if (S == 0) return RDCNN_OK;
     int cpl = h->adj_cpl, depth = h->adj_depth, seg = h->adj_seg_rows;
-    if (depth == 0) adj_auto_config(h, &cpl, &depth, &seg);
+    if (depth == 0) adj_even_auto_config(h, &cpl, &depth, &seg);
     // Paired passes: an even depth of 2..8, one or two columns per lane.
     if (cpl > 2) cpl = 2;
     if (depth > 8) depth = 8;
