@@ -30,9 +30,17 @@ R = C = 4096
 T_CHUNK = 10000
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL_UPDATE = 16  # read u, v and write u, v once per explicit step
-FLOPS_PER_CELL_UPDATE = 27  # 6 add + 1 mul + 10 fma of Eq. (1)-(3) in the kernels' order
+# Algorithmic flops of one cell-update of Eq. (1)-(3): two 5-point Laplacians
+# (3 adds + 1 fma each), u^3 and f1, f2 and the two Euler updates: 28 flops
+# (an fma counts 2).  The kernels' rounding order issues 17 VALU instructions.
+FLOPS_PER_CELL_UPDATE = 28
 VALU_OPS_PER_CELL_UPDATE = 17
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: one non-packed VALU op per lane per clock
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz.  The published FP32 vector
+# peak, 157.3 TFLOP/s, counts packed (two-wide) FMAs; without packed FP32 the
+# ceiling is one FMA per lane per clock, 78.6 TFLOP/s, and the issue rate is
+# 39.3 T lane-instructions/s.
+ALU_PEAK_TFLOPS = 157.3
+ALU_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
@@ -91,9 +99,14 @@ def _timed(fn, stream):
 def bench_fwd_bwd(stream):
     """Differentiation workload: 1024x1024, T = 2000, plain gene, x ~ U[-1,1]
     (seed 0), loss = MSE(u_T, three-sinusoid stripe target); gradients with
-    respect to x and all eight parameters."""
+    respect to x, Du, Dv and eps (and, separately, all eight parameters).
+    Schedules: checkpoint every ceil(sqrt(T)) steps (rounded up to the pass
+    depth: 48) and recompute each segment in the backward, overlapped with
+    the reverse pass of the segment after it (the workload's schedule), and
+    the whole trajectory recorded in the forward."""
     import torch
     from paper_2102_10340_amd import Simulation, simulate
+    from paper_2102_10340_amd import autograd as AG
     N, T = 1024, 2000
     g = W.PLAIN_GENE
     keys = ("dt", "a", "b", "eps", "c", "k3", "Du", "Dv")
@@ -106,26 +119,38 @@ def bench_fwd_bwd(stream):
         sim.read()
         sim.close()
 
-    def fwd_bwd(grads):
-        xt = x.clone().requires_grad_(True)
-        theta = torch.tensor([g[k] for k in keys], dtype=torch.float64, requires_grad=True)
-        u, _ = simulate(xt, theta, T, "zeroflux", grads=grads)
-        ((u - target) ** 2).mean().backward()
+    def fwd_bwd(grads, S):
+        def run():
+            xt = x.clone().requires_grad_(True)
+            theta = torch.tensor([g[k] for k in keys], dtype=torch.float64, requires_grad=True)
+            u, _ = simulate(xt, theta, T, "zeroflux", S=S, grads=grads)
+            ((u - target) ** 2).mean().backward()
+        return run
+
+    def best(fn, n=3):
+        fn()
+        return min(_timed(fn, stream) for _ in range(n))
 
     sub = ("Du", "Dv", "eps")
-    fwd()
-    fwd_bwd(sub)
-    fwd_bwd(None)
-    tf = min(_timed(fwd, stream) for _ in range(3))
-    tfb = min(_timed(lambda: fwd_bwd(sub), stream) for _ in range(3))
-    tfb8 = min(_timed(lambda: fwd_bwd(None), stream) for _ in range(3))
+    tf = best(fwd)
+    S = AG.default_segment(T)
+    t_sq = best(fwd_bwd(sub, 0))
+    t_sq8 = best(fwd_bwd(None, 0))
+    t_wh = best(fwd_bwd(sub, -1))
     cells = N * N * T
     return {"workload": "1024x1024 zero-flux, T=2000, MSE to stripe target, grads wrt x, Du, Dv "
-                        "and eps; states of even times recorded in HBM, odd ones rebuilt in the "
-                        "reverse passes",
-            "fwd_gcells": cells / tf / 1e9, "fwd_bwd_gcells": cells / tfb / 1e9,
-            "fwd_ms": tf * 1e3, "fwd_bwd_ms": tfb * 1e3, "ratio_fwd_bwd_to_fwd": tfb / tf,
-            "fwd_bwd_all8_ms": tfb8 * 1e3, "ratio_all8_to_fwd": tfb8 / tf}
+                        "and eps",
+            "fwd_ms": tf * 1e3, "fwd_gcells": cells / tf / 1e9,
+            "sqrt_t": {"schedule": f"checkpoint every {S} steps (ceil(sqrt(T)) rounded up to the "
+                                   "pass depth), segments recomputed on a second stream "
+                                   "overlapping the reverse pass of the next segment",
+                       "segment_steps": S, "fwd_bwd_ms": t_sq * 1e3,
+                       "fwd_bwd_gcells": cells / t_sq / 1e9, "ratio_fwd_bwd_to_fwd": t_sq / tf,
+                       "all8_ms": t_sq8 * 1e3, "ratio_all8_to_fwd": t_sq8 / tf},
+            "whole_trajectory": {"schedule": "states of even times of all T steps recorded in HBM",
+                                 "fwd_bwd_ms": t_wh * 1e3, "fwd_bwd_gcells": cells / t_wh / 1e9,
+                                 "ratio_fwd_bwd_to_fwd": t_wh / tf},
+            "ratio_fwd_bwd_to_fwd": t_sq / tf}
 
 
 def bench_batched(stream, per_class=4):
@@ -297,10 +322,11 @@ def bench_plain(stream):
     x = torch.from_numpy(W.uniform_x(N, N, 0)).cuda()
     sim = Simulation(x, W.PLAIN_GENE, "zeroflux")
     sim.step(T)
+    state = sim.read_host()  # s_T, compared with the oracle in the CPU leg
     t = min(_timed(lambda: sim.step(T), stream) for _ in range(3))
     sim.close()
     return {"workload": "256x256 zero-flux, T=1000, x~U[-1,1]", "gcells": N * N * T / t / 1e9,
-            "ms": t * 1e3}
+            "ms": t * 1e3}, state
 
 
 def bench_edge_fit(stream, n_img=64, iters=4):
@@ -389,20 +415,32 @@ def bench_edge_fit(stream, n_img=64, iters=4):
 PAPER_TABLE1_PYCUDA = {128: 470, 256: 1941, 512: 7581, 1024: 13059, 2048: 14198, 4096: 14545}
 
 
-def bench_paper_table1(stream):
+def bench_paper_table1(stream, nsnp=5):
     """The paper's Table I workload: the default gene (a=-0.3, b=1.3, eps=-0.1,
     c=1, k3=1/3, Du=0.06, Dv=1, dt=0.1), periodic boundary, random 11x11 centre
-    patch, 10^4 iterations, N = 128 ... 4096; Mcells/s next to the paper's
-    PyCUDA figures (P100)."""
+    patch, 10^4 iterations, N = 128 ... 4096, with the paper's main-loop
+    snapshots: nsnp = 5 snapshots, one every test_mod = 10^4 / 5 iterations,
+    kept in device memory (Sec. II.B main loop; the paper copies them to the
+    host).  Mcells/s (snapshots included) next to the paper's PyCUDA figures
+    (P100)."""
     import torch
     from paper_2102_10340_amd import Simulation
     T = 10000
-    out = {}
+    test_mod = T // nsnp
+    out = {"snapshots": nsnp, "test_mod": test_mod}
     for N, ref in PAPER_TABLE1_PYCUDA.items():
         x = torch.from_numpy(W.centre_patch_x(N, N, 11, 0)).cuda()
         sim = Simulation(x, W.gene(W.PAPER_DEFAULT_GENE), "periodic")
+        snaps = torch.empty((nsnp + 1, 2, N, N), dtype=torch.float32, device="cuda")
+
+        def job():
+            sim.read_into(snaps[0, 0], snaps[0, 1])
+            for k in range(nsnp):
+                sim.step(test_mod)
+                sim.read_into(snaps[k + 1, 0], snaps[k + 1, 1])
+
         sim.step(200)
-        t = _timed(lambda: sim.step(T), stream)
+        t = _timed(job, stream)
         sim.close()
         rate = N * N * T / t / 1e6
         out[str(N)] = {"mcells_s": rate, "s": t, "paper_pycuda_p100_mcells_s": ref,
@@ -410,26 +448,107 @@ def bench_paper_table1(stream):
     return out
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_rate(fn, cells_per_step, budget_s, max_steps=2000):
+    """Cell-updates/s of fn(n) (n oracle steps), n sized to about budget_s."""
+    t0 = time.perf_counter()
+    fn(2)
+    per = (time.perf_counter() - t0) / 2
+    n = int(max(2, min(max_steps, budget_s / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    fn(n)
+    dt = time.perf_counter() - t0
+    return cells_per_step * n / dt, n
+
+
 def cpu_baseline(budget_s: float):
-    """The oracle (float32, OpenMP rows) on a bounded sample of the same workload:
-    the 4096x4096 grid and initial state, for as many steps as fit the budget."""
+    """The oracle (plain C loops, float32, OpenMP over rows) on a bounded sample
+    of the same workload: the 4096x4096 slow-growth grid and initial state, for
+    as many steps as fit the budget, on all the host's OpenMP threads and on
+    one thread."""
     import oracle
     x = W.centre_patch_x(R, C, 16, 0)
     u, v = oracle.init_state(x, 1.0)
+    nthr = oracle.num_threads()
+
+    def run(n):
+        oracle.run(u, v, W.PLAIN_GENE, "zeroflux", n, "f32")
+
+    rate, n = _oracle_rate(run, R * C, budget_s * 0.7)
+    oracle.set_num_threads(1)
+    try:
+        rate1, n1 = _oracle_rate(run, R * C, budget_s * 0.3)
+    finally:
+        oracle.set_num_threads(nthr)
+    return {"value": rate / 1e9, "unit": "Gcell-updates/s", "cores": nthr, "kind": "oracle",
+            "sample": f"4096x4096 slow-growth grid from the job's initial state, {n} steps "
+                      f"(float32 oracle, {nthr} OpenMP threads)",
+            "one_thread": {"value": rate1 / 1e9, "steps": n1}, "cpu_model": _cpu_model()}
+
+
+def oracle_workloads(gpu_plain_state=None):
+    """The oracle timed on the other workloads (all OpenMP threads): the plain
+    method at full T (float32, plus the float64 run that states the float32
+    drift), a 32-instance subset of the parameter sweep (200 steps each), and
+    the differentiation workload's forward plus its float64 reverse pass."""
+    import oracle
+    out = {"cores": oracle.num_threads(), "cpu_model": _cpu_model()}
+    # plain method, 256^2, T = 1000
+    x = W.uniform_x(256, 256, 0)
+    u0, v0 = oracle.init_state(x, 1.0)
     t0 = time.perf_counter()
-    u, v = oracle.run(u, v, W.PLAIN_GENE, "zeroflux", 2, "f32")
-    per = (time.perf_counter() - t0) / 2
-    n = int(max(2, min(2000, budget_s / max(per, 1e-6))))
+    u32 = oracle.run(u0, v0, W.PLAIN_GENE, "zeroflux", 1000, "f32")
+    t32 = time.perf_counter() - t0
+    u64 = oracle.run(u0, v0, W.PLAIN_GENE, "zeroflux", 1000, "f64")
+    drift = max(float(np.abs(u32[0] - u64[0]).max()), float(np.abs(u32[1] - u64[1]).max()))
+    plain = {"gcells": 256 * 256 * 1000 / t32 / 1e9, "s": t32,
+             "float32_vs_float64_drift_T1000": drift}
+    if gpu_plain_state is not None:
+        plain["gpu_equals_float32_oracle_bitwise"] = bool(
+            np.array_equal(gpu_plain_state[0], u32[0]) and np.array_equal(gpu_plain_state[1], u32[1]))
+    out["plain_256_T1000"] = plain
+    # parameter sweep: the first 32 instances, 200 steps each
+    inst = W.sweep_instances(1024, 0)[:32]
+    T = 200
     t0 = time.perf_counter()
-    oracle.run(u, v, W.PLAIN_GENE, "zeroflux", n, "f32")
-    dt = time.perf_counter() - t0
-    return {"value": R * C * n / dt / 1e9, "unit": "Gcell-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"4096x4096 slow-growth grid, steps 3..{n + 2} of the job, float32 oracle"}
+    cells = 0
+    for d in inst:
+        xi = W.uniform_x(d["rows"], d["cols"], d["seed"])
+        oracle.run(*oracle.init_state(xi, 1.0), d["gene"], "zeroflux", T, "f32")
+        cells += d["rows"] * d["cols"] * T
+    ts = time.perf_counter() - t0
+    out["sweep_32_instances_T200"] = {"gcells": cells / ts / 1e9, "s": ts}
+    # differentiation workload: forward (float32) + float64 reverse pass
+    N, T = 1024, 2000
+    x = W.uniform_x(N, N, 0)
+    tgt = W.stripe_target(N, N, 0)
+    t0 = time.perf_counter()
+    uT = oracle.run(*oracle.init_state(x, 1.0), W.PLAIN_GENE, "zeroflux", T, "f32")[0]
+    tf = time.perf_counter() - t0
+    lam = 2.0 * (uT.astype(np.float64) - tgt) / (N * N)
+    t0 = time.perf_counter()
+    oracle.grad(x, x, W.PLAIN_GENE, "zeroflux", T, lam, np.zeros_like(lam), traj="f32")
+    tb = time.perf_counter() - t0
+    out["differentiation_1024_T2000"] = {"fwd_s": tf, "fwd_gcells": N * N * T / tf / 1e9,
+                                         "float64_reverse_pass_s": tb,
+                                         "fwd_bwd_gcells": N * N * T / (tf + tb) / 1e9}
+    return out
 
 
 def main():
     args = parse()
+    plain_state = None
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the simulator runs on a single MI355X)", file=sys.stderr)
@@ -479,9 +598,12 @@ def main():
     rate = R * C * steps_total / (ms / 1e3)  # cell-updates / s
     launches = args.steps * (-(-chunk // depth))
     launch_s = ms / 1e3 / launches  # upper bound: includes the snapshot copies
-    achieved_gbs = BYTES_PER_CELL_UPDATE * R * C * depth / launch_s / 1e9
+    cells_per_launch = R * C * depth
+    tflops = FLOPS_PER_CELL_UPDATE * cells_per_launch / launch_s / 1e12
+    eff_gbs = BYTES_PER_CELL_UPDATE * cells_per_launch / launch_s / 1e9
     alive = float(snaps[-1, 0].abs().max())
     traffic = measured_traffic(f"void rd::stream_step_kernel<4, {depth}, 0>")
+    pass_min = 16 * R * C  # one read and one write of the state per pass
 
     out = {
         "metric": "Gcell-updates/s FP32 forward (slow-growth 4096^2) + % of HBM roofline",
@@ -501,16 +623,28 @@ def main():
                                "device snapshot", "time_steps_per_step": chunk,
                    "grid": [R, C], "kernel": f"stream_step_kernel<4,{depth},0>",
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                                     "copy-calibrated)",
-                     "traffic_gbs": None if traffic is None else traffic / launch_s / 1e9,
-                     "basis": "16 B per cell-update x R*C*depth cell-updates per launch / mean "
-                              "launch time (HIP events over the timed region)"},
-        "valu": {"achieved_tops": VALU_OPS_PER_CELL_UPDATE * rate / 1e12, "peak_tops": VALU_PEAK_TOPS,
-                 "frac": VALU_OPS_PER_CELL_UPDATE * rate / 1e12 / VALU_PEAK_TOPS,
-                 "tflops": FLOPS_PER_CELL_UPDATE * rate / 1e12},
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS, "traffic": traffic,
+                     "basis": f"{FLOPS_PER_CELL_UPDATE} algorithmic flops per cell-update x "
+                              f"R*C*{depth} cell-updates per launch / mean launch time (HIP events "
+                              "over the timed region, snapshot copies included)",
+                     "peak_nonpacked": ALU_NONPACKED_TFLOPS,
+                     "frac_nonpacked": tflops / ALU_NONPACKED_TFLOPS,
+                     "issue": {"valu_instructions_per_cell_update": VALU_OPS_PER_CELL_UPDATE,
+                               "achieved_tops": VALU_OPS_PER_CELL_UPDATE * cells_per_launch
+                               / launch_s / 1e12,
+                               "peak_tops": VALU_PEAK_TOPS,
+                               "frac": VALU_OPS_PER_CELL_UPDATE * cells_per_launch / launch_s
+                               / 1e12 / VALU_PEAK_TOPS},
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-calibrated); null if the kernel changed since",
+                     "measured_hbm": None if traffic is None else {
+                         "gbs": traffic / launch_s / 1e9,
+                         "frac": traffic / launch_s / 1e9 / HBM_PEAK_GBS,
+                         "traffic_over_pass_minimum": traffic / pass_min,
+                         "pass_minimum_bytes": pass_min},
+                     "effective_hbm": {"basis": "16 B per cell-update (the naive step's traffic)",
+                                       "gbs": eff_gbs, "frac": eff_gbs / HBM_PEAK_GBS}},
         "host_wall_s": t_host,
         "final_max_abs_u": alive,
     }
@@ -529,13 +663,15 @@ def main():
             if args.only_extra in (None, "models"):
                 out["models"] = bench_models(stream)
             if args.only_extra in (None, "plain"):
-                out["plain"] = bench_plain(stream)
+                out["plain"], plain_state = bench_plain(stream)
             if args.only_extra in (None, "edge"):
                 out["edge_fit"] = bench_edge_fit(stream)
             if args.only_extra in (None, "table1"):
                 out["paper_table1"] = bench_paper_table1(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        if not args.no_extra and args.only_extra is None:
+            out["cpu_baseline"]["workloads"] = oracle_workloads(plain_state)
     print(json.dumps(out), flush=True)
 
 

@@ -47,10 +47,11 @@ enum {
 
 enum {
     RDCNN_OK = 0,
-    RDCNN_EINVAL = -1, /* bad argument: null pointer, size < 1, T < 0, non-finite parameter */
-    RDCNN_EHIP = -2,   /* a HIP runtime call or kernel launch failed */
-    RDCNN_ENOMEM = -3, /* host or device allocation of an internal workspace failed */
-    RDCNN_ESTATE = -4  /* call not valid for this handle's state */
+    RDCNN_EINVAL = -1,     /* bad argument: null pointer, size < 1, T < 0, non-finite parameter */
+    RDCNN_EHIP = -2,       /* a HIP runtime call or kernel launch failed */
+    RDCNN_ENONFINITE = -3, /* a checked read found NaN or infinite values in the state */
+    RDCNN_ESTATE = -4,     /* call not valid for this handle's state */
+    RDCNN_ENOMEM = -5      /* host or device allocation of an internal workspace failed */
 };
 
 /* Gene of Sec. II.A (the paper's Pars vector: dt, a, b, eps, c, Du, Dv) plus
@@ -139,8 +140,19 @@ int rdcnn_step(rdcnn_t h, long long T);
  * Sec. II.B main loop) into u_dst and v_dst, rows*cols floats each.
  * dst_is_host != 0: host destinations; the call waits for the stream.
  * dst_is_host == 0: device destinations; asynchronous on the stream.
+ * With the finite check on (rdcnn_set_check_finite), the call also counts
+ * NaN and infinite values of the state on the device, waits for the stream,
+ * and returns RDCNN_ENONFINITE if there are any (the copy is made either way):
+ * the failure detection for runs that leave the stable range dt*max(Du,Dv) <=
+ * 1/4 or are given non-finite inputs.
+ * Errors: RDCNN_EINVAL (NULL argument), RDCNN_EHIP, RDCNN_ENONFINITE,
+ * RDCNN_ENOMEM (the check's 4-byte device counter, made on first use).
  */
 int rdcnn_read(rdcnn_t h, float *u_dst, float *v_dst, int dst_is_host);
+
+/* rdcnn_set_check_finite -- on != 0: later rdcnn_read calls check the state for
+ * NaN / Inf (above); 0 (the default): no check.  Errors: RDCNN_EINVAL. */
+int rdcnn_set_check_finite(rdcnn_t h, int on);
 
 /*
  * rdcnn_write_state -- replace the current state with (u_dev, v_dev), rows*cols
@@ -164,6 +176,15 @@ int rdcnn_current(rdcnn_t h, float **state_dev);
  *   Every setting gives bit-identical states.  Errors: RDCNN_EINVAL.
  */
 int rdcnn_set_kernel(rdcnn_t h, int kind, int depth, int cols_per_lane, int seg_rows);
+
+/*
+ * rdcnn_pass_config -- the pass shape later rdcnn_step calls use, with the
+ * automatic choices resolved: *kind 1 (one thread per cell) or 2 (streamed),
+ * *depth steps per pass, *cols_per_lane, *seg_rows output rows per wavefront
+ * (the paper's block/grid choice, Sec. II.B, made explicit).  Host-only, no
+ * device work.  Errors: RDCNN_EINVAL (NULL argument).
+ */
+int rdcnn_pass_config(rdcnn_t h, int *kind, int *depth, int *cols_per_lane, int *seg_rows);
 
 /*
  * rdcnn_step_record -- like rdcnn_step, and also writes the state each of the T
@@ -227,6 +248,60 @@ int rdcnn_adjoint_even(rdcnn_t h, const float *states_dev, long long S, float *a
                        float *adj_tmp_dev, double *dtheta_dev);
 
 /*
+ * rdcnn_step_checkpoints -- rdcnn_step for T steps that also keeps a checkpoint
+ * every S steps: s_{t+jS} goes to ckpt_dev[j] for jS < T (ceil(T/S) states of
+ * 2*rows*cols floats; t = the handle's current time, so ckpt_dev[0] is a copy
+ * of the current state).  Passes end at every multiple of S, and the pass that
+ * ends there writes its output straight into the checkpoint (no extra copy).
+ * The forward half of checkpoint-and-recompute; rdcnn_step_bwd is the
+ * backward half.  ckpt_dev must not overlap the handle's state buffers.
+ * Asynchronous.  Errors: RDCNN_EINVAL (S < 1, T < 0, NULL or overlapping
+ * buffer, not a FitzHugh-Nagumo grid), RDCNN_EHIP.
+ */
+int rdcnn_step_checkpoints(rdcnn_t h, long long T, long long S, float *ckpt_dev);
+
+/*
+ * rdcnn_step_record_sparse -- rdcnn_step_record_even writing into a trajectory
+ * with one slot per time: s_{t+2i} goes to states_dev[2i] for 2i < T (slots
+ * of odd index are not written).  This is the layout rdcnn_step_bwd reads.
+ * states_dev: device, at least T+1 states of 2*rows*cols floats; it must not
+ * overlap the handle's state buffers (the passes read their input from it).
+ * Asynchronous.  Errors: RDCNN_EINVAL, RDCNN_EHIP.
+ */
+int rdcnn_step_record_sparse(rdcnn_t h, long long T, float *states_dev);
+
+/*
+ * rdcnn_step_bwd -- reverse pass through one recorded segment of S steps of
+ * Eq. (1)-(3): the transpose of the Jacobian of the explicit-Euler step (the
+ * paper gives the forward model only, Sec. II.A), for the gradient of a loss J
+ * of the state after the segment.  This is the backward half of
+ * checkpoint-and-recompute: restore a checkpoint s_{t0}, record the S steps
+ * after it, call rdcnn_step_bwd.
+ *   states_dev   [S+1][2][rows][cols] floats, device: states_dev[q] = s_{t0+q},
+ *                the state step q of the segment starts from.  Only the slots
+ *                of even q < S are read (rdcnn_step_record and
+ *                rdcnn_step_record_sparse both fill them); each reverse pass
+ *                rebuilds the odd-time states it needs from the even ones with
+ *                the forward cell update, bit-identical to the forward pass.
+ *                Slot S (the state after the segment, never needed) is
+ *                overwritten: it is the reverse passes' workspace.
+ *   S            steps (>= 0; 0 does nothing)
+ *   lam_dev      rows*cols floats: on entry dJ/du at t0+S, on return dJ/du at t0
+ *   mu_dev       rows*cols floats: the same for v (distinct from lam_dev)
+ *   dtheta_accum 8 device doubles: dJ/dp of this segment is ADDED, order dt, a,
+ *                b, eps, c, k3, Du, Dv, for the parameters of the gradient
+ *                mask (rdcnn_set_grad_mask); NaN for the others
+ * Uses the handle's parameters, boundary rule, stream and reverse-pass
+ * settings (rdcnn_set_adjoint_kernel: an even depth of 2..8, one or two
+ * columns per lane).  The per-tile partial sums come from the process-wide
+ * pool described at rdcnn_adjoint.  Deterministic.  Asynchronous.
+ * Errors: RDCNN_EINVAL (NULL or overlapping buffers, S < 0, not a
+ * FitzHugh-Nagumo grid), RDCNN_ENOMEM, RDCNN_EHIP.
+ */
+int rdcnn_step_bwd(rdcnn_t h, float *states_dev, long long S, float *lam_dev, float *mu_dev,
+                   double *dtheta_accum);
+
+/*
  * rdcnn_set_adjoint_kernel -- pass settings for rdcnn_adjoint: `depth` reverse
  * steps per HBM pass, cols_per_lane 1 or 2 (depth 1..8) or 4 (depth 1..6), seg_rows
  * output rows per wavefront (0 = automatic).  depth = cols_per_lane = 0 restores
@@ -286,6 +361,21 @@ int rdcnn_batch_step(rdcnn_batch_t b, long long T);
 
 /* rdcnn_batch_current -- the packed buffer holding the current states. */
 int rdcnn_batch_current(rdcnn_batch_t b, float **state_dev);
+
+/*
+ * rdcnn_batch_read -- copy the current packed state (buf_floats floats, every
+ * instance at its offset) to dst_packed_dev (device memory, not overlapping the
+ * batch's buffers): the batch's snapshot (Sec. II.B main loop).  Asynchronous
+ * on the batch's stream, unless the finite check is on
+ * (rdcnn_batch_set_check_finite): then every instance's cells are checked for
+ * NaN / Inf on the device, the call waits, and returns RDCNN_ENONFINITE if any
+ * are found.  Errors: RDCNN_EINVAL, RDCNN_EHIP, RDCNN_ENONFINITE, RDCNN_ENOMEM.
+ */
+int rdcnn_batch_read(rdcnn_batch_t b, float *dst_packed_dev);
+
+/* rdcnn_batch_set_check_finite -- on != 0: rdcnn_batch_read checks for NaN /
+ * Inf (above).  Errors: RDCNN_EINVAL. */
+int rdcnn_batch_set_check_finite(rdcnn_batch_t b, int on);
 
 /*
  * rdcnn_batch_set_kernel -- steps per pass (depth), cols_per_lane (1, 2 or 4) and
@@ -352,7 +442,8 @@ int rdcnn_batch_set_adjoint_kernel(rdcnn_batch_t b, int depth, int cols_per_lane
  * return dJ/ds before them, per instance (u plane then v plane).  adj_tmp:
  * scratch of buf_floats floats.  dtheta (device, n x 8 doubles,
  * instance-major, order dt, a, b, eps, c, k3, Du, Dv): each instance's
- * parameter gradients are added to its row; gradients whose bit is clear in
+ * parameter gradients are added to its row (or, with rdcnn_batch_set_shared_grad,
+ * their sum over instances to dtheta[0 .. 8)); gradients whose bit is clear in
  * mask are not formed and come back NaN.  Sums are folded per instance in a
  * fixed order (deterministic).  The first call allocates the tile list and the
  * per-tile partial buffer (kept until destroy).  Errors: RDCNN_EINVAL (NULL or
@@ -361,6 +452,16 @@ int rdcnn_batch_set_adjoint_kernel(rdcnn_batch_t b, int depth, int cols_per_lane
  */
 int rdcnn_batch_adjoint(rdcnn_batch_t b, const float *traj, long long S, float *adj,
                         float *adj_tmp, unsigned mask, double *dtheta);
+
+/*
+ * rdcnn_batch_set_shared_grad -- on != 0: the batch's instances share one
+ * parameter vector (the edge-detection fit), and rdcnn_batch_adjoint[_even]
+ * add the gradient of that vector to dtheta[0 .. 8): the per-instance
+ * gradients summed on the device over instances 0 .. n-1 in index order
+ * (deterministic).  0 (the default): one row per instance, dtheta[8 i ..].
+ * Errors: RDCNN_EINVAL.
+ */
+int rdcnn_batch_set_shared_grad(rdcnn_batch_t b, int on);
 
 /*
  * rdcnn_batch_step_record_even -- rdcnn_batch_step_record keeping only the

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "librdcnn.so")
 BC = {"periodic": 0, "zeroflux": 1}
 PARAM_FIELDS = ("dt", "a", "b", "eps", "c", "k3", "Du", "Dv")
 
-OK, EINVAL, EHIP, ENOMEM, ESTATE = 0, -1, -2, -3, -4
+OK, EINVAL, EHIP, ENONFINITE, ESTATE, ENOMEM = 0, -1, -2, -3, -4, -5
 
 
 class RDCNNError(RuntimeError):
@@ -41,6 +41,7 @@ lib = ctypes.CDLL(LIB_PATH)
 _I, _LL, _P, _F = ctypes.c_int, ctypes.c_longlong, ctypes.c_void_p, ctypes.c_float
 _PP = ctypes.POINTER(ctypes.c_void_p)
 _PAR = ctypes.POINTER(Params)
+_PI = ctypes.POINTER(ctypes.c_int)
 
 _SIGS = {
     "rdcnn_create": [_PP, _I, _I, _I, _PAR, _P, _F, _P, _P, _P],
@@ -51,17 +52,25 @@ _SIGS = {
     "rdcnn_set_params": [_P, _PAR],
     "rdcnn_current": [_P, _PP],
     "rdcnn_set_kernel": [_P, _I, _I, _I, _I],
+    "rdcnn_pass_config": [_P, _PI, _PI, _PI, _PI],
     "rdcnn_destroy": [_P],
     "rdcnn_step_record": [_P, _LL, _P],
     "rdcnn_adjoint": [_P, _P, _LL, _P, _P, _P],
     "rdcnn_step_record_even": [_P, _LL, _P],
     "rdcnn_adjoint_even": [_P, _P, _LL, _P, _P, _P],
+    "rdcnn_step_record_sparse": [_P, _LL, _P],
+    "rdcnn_step_checkpoints": [_P, _LL, _LL, _P],
+    "rdcnn_step_bwd": [_P, _P, _LL, _P, _P, _P],
+    "rdcnn_set_check_finite": [_P, _I],
     "rdcnn_set_adjoint_kernel": [_P, _I, _I, _I],
     "rdcnn_init_backward": [_P, _LL, _F, _P, _P],
     "rdcnn_set_grad_mask": [_P, ctypes.c_uint],
     "rdcnn_batch_create": [_PP, _I, _P, _P, _P, _P, _I, _P, _P, _F, _P, _P, _LL, _P],
     "rdcnn_batch_step": [_P, _LL],
     "rdcnn_batch_current": [_P, _PP],
+    "rdcnn_batch_read": [_P, _P],
+    "rdcnn_batch_set_check_finite": [_P, _I],
+    "rdcnn_batch_set_shared_grad": [_P, _I],
     "rdcnn_batch_set_kernel": [_P, _I, _I, _I],
     "rdcnn_batch_use_graph": [_P, _I],
     "rdcnn_batch_use_lds": [_P, _I],

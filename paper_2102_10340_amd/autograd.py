@@ -1,23 +1,24 @@
 """Differentiable RD-CNN runs: torch.autograd.Function wrappers around the
-library's forward, state-recording and adjoint kernels.
+library's forward, checkpointing, recording and reverse-pass calls.
 
-Both schedules keep only the states of even times (rdcnn_step_record_even,
-4 bytes per cell and step); the paired reverse passes (rdcnn_adjoint_even)
-rebuild each odd state from the even one before it with the forward cell
-update, bit-identical to the forward pass, so the gradients equal those of a
-fully recorded trajectory.  The schedule is chosen by S:
-* S = -1, whole trajectory: the forward records the even states and the
-  backward runs the adjoint straight through them.  An MI355X has 288 GB of
-  HBM, so this is the default whenever the trajectory fits a quarter of the
-  free device memory (8 GiB for 1024x1024 x 2000 steps).
-* S > 0, checkpoint-and-recompute: the forward keeps one checkpoint every S
-  steps; the backward walks the segments from last to first, restores a
-  checkpoint, re-runs the segment while recording its even states and runs the
-  adjoint through them.  With S near sqrt(T) memory is O(sqrt(T)) states; the
-  default S is ceil(sqrt(T)) capped so that one segment's states stay within
-  half of the 256 MB last-level cache, where the adjoint reads them right after
-  they are written.
-S = 0 picks the whole trajectory if it fits, else the checkpointed schedule.
+The reverse pass is rdcnn_step_bwd: it reads the states of even times of a
+recorded segment and rebuilds each odd state from the even one before it with
+the forward cell update, bit-identical to the forward pass, so the gradients
+equal those of a fully recorded trajectory.  The schedule is chosen by S:
+* S = 0 (default) or S > 0, checkpoint-and-recompute (the differentiation
+  workload's schedule): the forward keeps one checkpoint every S steps
+  (rdcnn_step_checkpoints; each is written by the pass that ends there); the
+  backward walks the segments from last to first, restores a checkpoint,
+  re-runs the segment recording its even states (rdcnn_step_record_sparse)
+  and runs rdcnn_step_bwd through them.  The recompute of segment k needs only
+  checkpoint k, so it runs on a second stream while the reverse pass of
+  segment k+1 runs on the caller's stream (two segment buffers in turn).
+  S = 0 picks S = ceil(sqrt(T)) rounded up to the forward's pass depth of 8,
+  so checkpoints fall on pass boundaries: O(sqrt(T)) states of memory.
+* S = -1, whole trajectory: the forward records the even states of all T
+  steps and the backward runs rdcnn_step_bwd straight through them (memory
+  O(T) states; an MI355X's 288 GB holds 1024x1024 x 2000 steps many times).
+With no input needing a gradient the forward records nothing.
 
 Parameters travel as a tensor theta of 8 values in the order
 (dt, a, b, eps, c, k3, Du, Dv), the paper's gene (Sec. II.A) plus the cubic
@@ -32,25 +33,23 @@ import torch
 from ._lib import PARAM_FIELDS
 from .sim import Simulation, init_backward
 
-LLC_BYTES = 256 << 20
+PASS_DEPTH = 8  # steps per pass of the library's forward kernels
 
 
-def default_segment(T: int, rows: int, cols: int) -> int:
-    """ceil(sqrt(T)), capped so that a segment's even states fit half the last-level cache."""
+def default_segment(T: int) -> int:
+    """ceil(sqrt(T)) rounded up to a multiple of the forward pass depth."""
     s = max(1, math.ceil(math.sqrt(max(T, 1))))
-    cap = max(1, 2 * ((LLC_BYTES // 2) // (8 * rows * cols)))
-    return max(1, min(s, cap, T if T > 0 else 1))
+    s = -(-s // PASS_DEPTH) * PASS_DEPTH
+    return max(1, min(s, T if T > 0 else 1))
 
 
-def choose_schedule(T: int, rows: int, cols: int, S: int, device) -> int:
+def choose_schedule(T: int, rows: int, cols: int, S: int, device=None) -> int:
     """-1 (record the whole trajectory) or a checkpoint spacing > 0."""
-    if S != 0:
-        return S
-    need = 8 * rows * cols * max((T + 1) // 2, 1)
-    free, _ = torch.cuda.mem_get_info(device)
-    if need <= free // 4:
+    if S < 0:
         return -1
-    return default_segment(T, rows, cols)
+    if S > 0:
+        return S
+    return default_segment(T)
 
 
 def grad_mask(grads) -> int:
@@ -70,46 +69,102 @@ def _gene(theta: torch.Tensor):
     return dict(zip(PARAM_FIELDS, vals))
 
 
-def _forward(sim: Simulation, T: int, S: int, dev):
-    if S < 0:  # whole trajectory, even times
-        states = torch.empty((max((T + 1) // 2, 1), 2, sim.rows, sim.cols), dtype=torch.float32,
-                             device=dev)
-        sim.step_record_even(T, states)
+_SIDE_STREAMS = {}
+
+
+def _side_stream(device) -> torch.cuda.Stream:
+    """One extra stream per device (default priority) for the recompute."""
+    key = torch.device(device).index or 0
+    s = _SIDE_STREAMS.get(key)
+    if s is None:
+        s = _SIDE_STREAMS[key] = torch.cuda.Stream(device)
+    return s
+
+
+def _forward(sim: Simulation, T: int, S: int, dev, record: bool = True):
+    """Run T steps; returns (u_T, v_T, saved states, number of segments)."""
+    R, C = sim.rows, sim.cols
+    if not record:
+        sim.step(T)
+        u, v = sim.read()
+        return u, v, None, 0
+    if S < 0:  # whole trajectory: even-time states in their own slots, slot T = workspace
+        states = torch.empty((T + 1, 2, R, C), dtype=torch.float32, device=dev)
+        sim.step_record_sparse(T, states)
         u, v = sim.read()
         return u, v, states, 0
     nseg = -(-T // S) if T > 0 else 0
-    ckpt = torch.empty((max(nseg, 1), 2, sim.rows, sim.cols), dtype=torch.float32, device=dev)
-    for k in range(nseg):
-        sim.read_into(ckpt[k, 0], ckpt[k, 1])
-        sim.step(min(S, T - k * S))
+    ckpt = torch.empty((max(nseg, 1), 2, R, C), dtype=torch.float32, device=dev)
+    sim.step_checkpoints(T, S, ckpt)
     u, v = sim.read()
     return u, v, ckpt, nseg
 
 
 def _backward(sim: Simulation, ckpt, nseg: int, T: int, S: int, gu, gv, dev, kernel=None,
-              mask: int = 0xFF):
+              mask: int = 0xFF, overlap: bool = True):
     R, C = sim.rows, sim.cols
-    adj = torch.empty((2, R, C), dtype=torch.float32, device=dev)
-    for k, gk in enumerate((gu, gv)):
-        if gk is None:
-            adj[k].zero_()
-        else:
-            adj[k].copy_(gk)
-    tmp = torch.empty_like(adj)
+    lam = gu.detach().contiguous().clone() if gu is not None else \
+        torch.zeros((R, C), dtype=torch.float32, device=dev)
+    mu = gv.detach().contiguous().clone() if gv is not None else \
+        torch.zeros((R, C), dtype=torch.float32, device=dev)
     dtheta = torch.zeros(8, dtype=torch.float64, device=dev)
     if kernel is not None:
         sim.set_adjoint_kernel(*kernel)
     sim.set_grad_mask(mask)
-    if S < 0:  # ckpt holds the whole even-time trajectory
-        sim.adjoint_even(ckpt, T, adj, tmp, dtheta)
-        return adj, dtheta
-    seg = torch.empty(((min(S, max(T, 1)) + 1) // 2, 2, R, C), dtype=torch.float32, device=dev)
-    for k in range(nseg - 1, -1, -1):
+    if S < 0:  # ckpt holds the whole trajectory's even-time states
+        sim.step_bwd(ckpt, T, lam, mu, dtheta)
+        return lam, mu, dtheta
+    Smax = min(S, max(T, 1))
+    if not overlap or nseg < 2:
+        seg = torch.empty((Smax + 1, 2, R, C), dtype=torch.float32, device=dev)
+        for k in range(nseg - 1, -1, -1):
+            L = min(S, T - k * S)
+            sim.write_state_packed(ckpt[k])
+            sim.step_record_sparse(L, seg)
+            sim.step_bwd(seg, L, lam, mu, dtheta)
+        return lam, mu, dtheta
+    # Recompute segment k on the side stream (its own handle) while the
+    # reverse pass of segment k+1 runs on the caller's stream; two segment
+    # buffers in turn, each re-recorded only after the reverse pass that
+    # read it has finished.
+    main = torch.cuda.current_stream(dev)
+    side = _side_stream(dev)
+    segs = [torch.empty((Smax + 1, 2, R, C), dtype=torch.float32, device=dev) for _ in range(2)]
+    side.wait_stream(main)
+    with torch.cuda.stream(side):
+        rsim = Simulation(ckpt[0, 0], sim.gene, sim.bc, 1.0)
+        rsim.set_kernel(*sim.kernel_setting())
+    done = [None, None]
+    for idx, k in enumerate(range(nseg - 1, -1, -1)):
         L = min(S, T - k * S)
-        sim.write_state_packed(ckpt[k])
-        sim.step_record_even(L, seg)
-        sim.adjoint_even(seg, L, adj, tmp, dtheta)
-    return adj, dtheta
+        b = idx % 2
+        with torch.cuda.stream(side):
+            if done[b] is not None:
+                side.wait_event(done[b])
+            rsim.write_state_packed(ckpt[k])
+            rsim.step_record_sparse(L, segs[b])
+            ready = torch.cuda.Event()
+            ready.record(side)
+        main.wait_event(ready)
+        sim.step_bwd(segs[b], L, lam, mu, dtheta)
+        done[b] = torch.cuda.Event()
+        done[b].record(main)
+    main.wait_stream(side)
+    rsim.close()
+    return lam, mu, dtheta
+
+
+def _release(ctx):
+    if ctx.sim is not None:
+        ctx.sim.close()
+    ctx.sim = None
+    ctx.ckpt = None
+
+
+def _check_once(ctx):
+    if ctx.sim is None:
+        raise RuntimeError("the saved trajectory of this RD-CNN run was released by its first "
+                           "backward; run the forward again to differentiate it again")
 
 
 class RDCNNFunction(torch.autograd.Function):
@@ -121,8 +176,12 @@ class RDCNNFunction(torch.autograd.Function):
         x = x.detach().contiguous()
         T = int(T)
         S = choose_schedule(T, x.shape[0], x.shape[1], int(S), x.device)
+        record = bool(ctx.needs_input_grad[0] or ctx.needs_input_grad[1])
         sim = Simulation(x, _gene(theta), bc, ka)
-        u, v, ckpt, nseg = _forward(sim, T, S, x.device)
+        u, v, ckpt, nseg = _forward(sim, T, S, x.device, record)
+        if not record:
+            sim.close()
+            sim = None
         ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S, ctx.ka = sim, ckpt, nseg, T, S, ka
         ctx.adj_kernel, ctx.mask = adj_kernel, mask
         ctx.theta_meta = (theta.dtype, theta.device)
@@ -130,11 +189,12 @@ class RDCNNFunction(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gu, gv):
+        _check_once(ctx)
         dev = ctx.ckpt.device
-        adj, dtheta = _backward(ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S, gu, gv, dev,
-                                ctx.adj_kernel, ctx.mask)
-        gx = init_backward(adj, ctx.ka)
-        ctx.sim.close()
+        lam, mu, dtheta = _backward(ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S, gu, gv, dev,
+                                    ctx.adj_kernel, ctx.mask)
+        gx = init_backward(torch.stack((lam, mu)), ctx.ka)
+        _release(ctx)
         dt, dd = ctx.theta_meta
         return gx, dtheta.to(device=dd, dtype=dt), None, None, None, None, None, None
 
@@ -149,8 +209,12 @@ class RDCNNStateFunction(torch.autograd.Function):
         v0 = v0.detach().contiguous()
         T = int(T)
         S = choose_schedule(T, u0.shape[0], u0.shape[1], int(S), u0.device)
+        record = bool(any(ctx.needs_input_grad[:3]))
         sim = Simulation.from_state(u0, v0, _gene(theta), bc)
-        u, v, ckpt, nseg = _forward(sim, T, S, u0.device)
+        u, v, ckpt, nseg = _forward(sim, T, S, u0.device, record)
+        if not record:
+            sim.close()
+            sim = None
         ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S = sim, ckpt, nseg, T, S
         ctx.adj_kernel, ctx.mask = adj_kernel, mask
         ctx.theta_meta = (theta.dtype, theta.device)
@@ -158,19 +222,20 @@ class RDCNNStateFunction(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gu, gv):
+        _check_once(ctx)
         dev = ctx.ckpt.device
-        adj, dtheta = _backward(ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S, gu, gv, dev,
-                                ctx.adj_kernel, ctx.mask)
-        ctx.sim.close()
+        lam, mu, dtheta = _backward(ctx.sim, ctx.ckpt, ctx.nseg, ctx.T, ctx.S, gu, gv, dev,
+                                    ctx.adj_kernel, ctx.mask)
+        _release(ctx)
         dt, dd = ctx.theta_meta
-        return (adj[0].clone(), adj[1].clone(), dtheta.to(device=dd, dtype=dt), None, None, None,
-                None, None)
+        return lam, mu, dtheta.to(device=dd, dtype=dt), None, None, None, None, None
 
 
 def simulate(x, theta, T, bc="zeroflux", ka=1.0, S=0, grads=None):
     """Differentiable T-step run from u = v = ka x; returns (u_T, v_T).
-    grads: parameter names whose gradients are formed (default all); the
-    others come back NaN in theta.grad."""
+    S: 0 checkpoint every ceil(sqrt(T)) steps (rounded up to 8), > 0 every S
+    steps, -1 record the whole trajectory.  grads: parameter names whose
+    gradients are formed (default all); the others come back NaN in theta.grad."""
     return RDCNNFunction.apply(x, theta, T, bc, ka, S, None, grad_mask(grads))
 
 
@@ -216,18 +281,22 @@ class RDCNNBatchFunction(torch.autograd.Function):
             nseg = -(-T // S) if T > 0 else 0
             store = torch.empty((max(nseg, 1), b.total), dtype=torch.float32, device=dev)
             for k in range(nseg):
-                store[k].copy_(b.current())
+                b.read_into(store[k])
                 b.step(min(S, T - k * S))
         outs = []
         for i in range(n):
             st = b.state(i)
             outs += [st[0].clone(), st[1].clone()]
+        b.set_shared_grad(th.dim() == 1)
         ctx.b, ctx.store, ctx.nseg, ctx.T, ctx.S, ctx.ka, ctx.mask = b, store, nseg, T, S, ka, mask
         ctx.theta_meta = (theta.dtype, theta.device, theta.dim())
         return tuple(outs)
 
     @staticmethod
     def backward(ctx, *gouts):
+        if ctx.b is None:
+            raise RuntimeError("the saved trajectory of this batch run was released by its "
+                               "first backward; run the forward again to differentiate it again")
         b, T, S = ctx.b, ctx.T, ctx.S
         adj = torch.zeros(b.total, dtype=torch.float32, device=b.device)
         for i in range(len(b)):
@@ -237,7 +306,11 @@ class RDCNNBatchFunction(torch.autograd.Function):
                 if gg is not None:
                     a[layer].copy_(gg)
         tmp = torch.empty_like(adj)
-        dtheta = torch.zeros((len(b), 8), dtype=torch.float64, device=adj.device)
+        dt, dd, dim = ctx.theta_meta
+        # shared parameters: the library sums the instances' gradients on the
+        # device in a fixed order (rdcnn_batch_set_shared_grad)
+        dtheta = torch.zeros((8,) if dim == 1 else (len(b), 8), dtype=torch.float64,
+                             device=adj.device)
         if S < 0:
             b.adjoint_even(ctx.store, T, adj, tmp, ctx.mask, dtheta)
         else:
@@ -250,11 +323,9 @@ class RDCNNBatchFunction(torch.autograd.Function):
                 b.adjoint_even(seg, L, adj, tmp, ctx.mask, dtheta)
         gxs = [init_backward(b.view(adj, i), ctx.ka) for i in range(len(b))]
         b.close()
-        dt, dd, dim = ctx.theta_meta
-        g = dtheta.cpu()
-        if dim == 1:  # shared parameters: sum over instances in a fixed order
-            g = g.sum(0)
-        return (g.to(device=dd, dtype=dt), None, None, None, None, None, *gxs)
+        ctx.b = None
+        ctx.store = None
+        return (dtheta.to(device=dd, dtype=dt), None, None, None, None, None, *gxs)
 
 
 def simulate_batch(xs, theta, T, bc="zeroflux", ka=1.0, S=0, grads=None):

@@ -56,6 +56,7 @@ class Batch:
         cxoff = (ctypes.c_longlong * n)(*xoffs)
         pars = (Params * n)(*[Params.from_mapping(g) for g in genes])
         self._h = ctypes.c_void_p()
+        self._shared = False
         with torch.cuda.device(self.device):
             check(lib.rdcnn_batch_create(ctypes.byref(self._h), n, rows, cols, coff, pars, BC[bc],
                                          self._x.data_ptr(), cxoff, float(ka),
@@ -152,8 +153,28 @@ class Batch:
         for t in (adj, adj_tmp):
             if t.dtype != torch.float32 or t.numel() < self.total or not t.is_contiguous():
                 raise ValueError("adj buffers must be contiguous float32 of the batch's size")
-        if dtheta.dtype != torch.float64 or tuple(dtheta.shape) != (len(self), 8) or not dtheta.is_contiguous():
-            raise ValueError("dtheta must be contiguous float64 [n, 8]")
+        want = (8,) if self._shared else (len(self), 8)
+        if dtheta.dtype != torch.float64 or tuple(dtheta.shape) != want or not dtheta.is_contiguous():
+            raise ValueError(f"dtheta must be contiguous float64 {list(want)}")
+
+    def set_shared_grad(self, on: bool = True) -> None:
+        """The instances share one parameter vector: adjoint() then adds the
+        gradient summed over instances (on the device, in instance order) to a
+        float64 [8] dtheta instead of one row per instance."""
+        check(lib.rdcnn_batch_set_shared_grad(self._h, 1 if on else 0))
+        self._shared = bool(on)
+
+    def set_check_finite(self, on: bool = True) -> None:
+        """read_into() checks every instance for NaN / Inf (RDCNN_ENONFINITE)."""
+        check(lib.rdcnn_batch_set_check_finite(self._h, 1 if on else 0))
+
+    def read_into(self, dst: torch.Tensor) -> None:
+        """Copy the current packed state into dst (float32 [>= total] on the
+        device; rdcnn_batch_read)."""
+        if dst.dtype != torch.float32 or dst.numel() < self.total or not dst.is_contiguous() \
+                or dst.device != self.device:
+            raise ValueError("dst must be contiguous float32 of the batch's size on its device")
+        check(lib.rdcnn_batch_read(self._h, dst.data_ptr()))
 
     def view(self, packed: torch.Tensor, i: int) -> torch.Tensor:
         """View [2, R, C] of instance i in a packed tensor of this batch's layout."""
@@ -163,7 +184,9 @@ class Batch:
 
     def snapshot(self) -> torch.Tensor:
         """A copy of the current packed state (for the change statistics)."""
-        return self.current().clone()
+        out = torch.empty(self.total, dtype=torch.float32, device=self.device)
+        self.read_into(out)
+        return out
 
     STAT_NAMES = ("mean_u", "var_u", "mean_v", "var_v", "frac_far", "frac_moving",
                   "max_change", "rms_change")

@@ -1,6 +1,7 @@
 """Build librdcnn.so (the HIP kernels and the C ABI) in-tree for gfx950.
 
-Run ``python -m paper_2102_10340_amd.build``.  Every source is compiled with:
+Run ``python -m paper_2102_10340_amd.build`` (``--changed``: recompile only
+sources older than their inputs).  Every source is compiled with:
   -ffp-contract=off                    no fusion beyond the explicit fmaf calls,
                                        so the float32 rounding order is fixed
   -fno-gpu-flush-denormals-to-zero     IEEE denormals, as on the host
@@ -37,12 +38,42 @@ def _hipcc() -> str:
     return os.path.join(rocm, "bin", "hipcc")
 
 
-def build(verbose: bool = False) -> str:
+def _deps(path: str, seen=None) -> set:
+    """The file and every header of csrc/ or include/ it includes, transitively."""
+    import re
+    seen = set() if seen is None else seen
+    if path in seen:
+        return seen
+    seen.add(path)
+    with open(path) as f:
+        for name in re.findall(r'^\s*#\s*include\s+"([^"]+)"', f.read(), flags=re.M):
+            for d in (CSRC, INCLUDE):
+                q = os.path.join(d, name)
+                if os.path.exists(q):
+                    _deps(q, seen)
+                    break
+    return seen
+
+
+def _stale(obj: str, src: str) -> bool:
+    """An object is stale if it is missing or older than its source or a
+    header the source includes."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in _deps(src))
+
+
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compile every source (force=False: only those older than their inputs)
+    and link librdcnn.so."""
     os.makedirs(OBJDIR, exist_ok=True)
     hipcc = _hipcc()
 
     def compile_one(src):
         obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+        if not force and not _stale(obj, os.path.join(CSRC, src)):
+            return obj
         cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -61,4 +92,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, force="--changed" not in sys.argv))

@@ -33,8 +33,8 @@ static_assert(NSUM == kAdjSums, "partial buffer layout");
 
 struct AdjArgs {
     TileArgs t;
-    const float *in;      // (lam, mu) of level 0, [2][R][C]
-    float *out;           // (lam, mu) after KB reverse steps
+    const float *in_l, *in_m;  // lam, mu of level 0, R x C each
+    float *out_l, *out_m;      // lam, mu after KB reverse steps
     const float *states;    // the KB states this pass reads, oldest first
     unsigned state_stride;  // bytes from one state to the next ([KB][2][R][C]: 8*R*C)
     Gene g;
@@ -111,8 +111,8 @@ __device__ __forceinline__ void adjoint_body(const AdjArgs &A, const Tile<CPL> &
     const int C = A.t.C, R = A.t.R, bc = A.t.bc;
     const unsigned pbytes = 4u * (unsigned)R * (unsigned)C;
     const unsigned rowb = 4u * (unsigned)C;
-    const Buf il(A.in, pbytes), im(A.in + (size_t)R * C, pbytes);
-    const Buf ol(A.out, pbytes), om(A.out + (size_t)R * C, pbytes);
+    const Buf il(A.in_l, pbytes), im(A.in_m, pbytes);
+    const Buf ol(A.out_l, pbytes), om(A.out_m, pbytes);
     const unsigned sstride = A.state_stride;
     const Buf sb(A.states, (unsigned)(KB - 1) * sstride + 2u * pbytes);
     const Gene g = A.g;
@@ -267,8 +267,8 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
     const int C = A.t.C, R = A.t.R, bc = A.t.bc;
     const unsigned pbytes = 4u * (unsigned)R * (unsigned)C;
     const unsigned rowb = 4u * (unsigned)C;
-    const Buf il(A.in, pbytes), im(A.in + (size_t)R * C, pbytes);
-    const Buf ol(A.out, pbytes), om(A.out + (size_t)R * C, pbytes);
+    const Buf il(A.in_l, pbytes), im(A.in_m, pbytes);
+    const Buf ol(A.out_l, pbytes), om(A.out_m, pbytes);
     const unsigned sstride = A.state_stride;  // E_p at (P-1-p) * sstride
     const Buf sb(A.states, (unsigned)(P - 1) * sstride + 2u * pbytes);
     const Gene g = A.g;
@@ -503,8 +503,10 @@ __device__ __forceinline__ void batch_tile_args(const BatchAdjArgs &B, int id, A
     A.t.ntiles = 0;
     A.t.per_xcd = 0;
     A.t.vec_ok = (in.C % CPL) == 0;
-    A.in = B.in + in.off;
-    A.out = B.out + in.off;
+    A.in_l = B.in + in.off;
+    A.in_m = A.in_l + (size_t)in.R * in.C;
+    A.out_l = B.out + in.off;
+    A.out_m = A.out_l + (size_t)in.R * in.C;
     A.states = B.states + in.off;
     A.state_stride = B.state_stride;
     A.g = in.g;
@@ -570,6 +572,17 @@ __global__ __launch_bounds__(256) void batch_adjoint_finish_kernel(const double 
         for (int k = 0; k < NSUM; ++k) S[k] += p[k];
     }
     add_grads(S, insts[i].g, mask, dtheta + 8 * (size_t)i);
+}
+
+// Shared parameters: dtheta[q] += sum over instances i = 0 .. n-1, in that
+// order, of rows[8 i + q] (one thread per parameter).
+__global__ __launch_bounds__(64) void grad_row_sum_kernel(const double *rows, int n, double *dtheta)
+{
+    const int q = threadIdx.x;
+    if (q >= 8) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += rows[8 * (size_t)i + q];
+    dtheta[q] += s;
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(double *p, long long n)
@@ -647,18 +660,20 @@ unsigned grid1(long long n)
 
 }  // namespace
 
-hipError_t launch_adjoint(const float *in, float *out, const float *states, long long q_top,
+hipError_t launch_adjoint(const AdjPlanes &io, const float *states, int every, long long q_top,
                           int R, int C, int bc, const Gene &g, const StreamGeom &geom,
                           double *partial, bool lam_sums, hipStream_t s)
 {
     AdjFn f = lam_sums ? pick_adj<true>(geom.cpl, geom.depth) : pick_adj<false>(geom.cpl, geom.depth);
-    if (!f || q_top < geom.depth - 1) return hipErrorInvalidValue;
+    if (!f || q_top < geom.depth - 1 || every < 1) return hipErrorInvalidValue;
     AdjArgs a;
     a.t = tile_args(R, C, bc, geom);
-    a.in = in;
-    a.out = out;
-    a.states = states + (q_top - geom.depth + 1) * 2LL * R * C;
-    a.state_stride = 8u * (unsigned)R * (unsigned)C;
+    a.in_l = io.in_l;
+    a.in_m = io.in_m;
+    a.out_l = io.out_l;
+    a.out_m = io.out_m;
+    a.states = states + (q_top - geom.depth + 1) * every * 2LL * R * C;
+    a.state_stride = 8u * (unsigned)every * (unsigned)R * (unsigned)C;
     a.g = g;
     a.partial = partial;
     hipLaunchKernelGGL(f, dim3((unsigned)(8 * geom.per_xcd)), dim3(64), 0, s, a);
@@ -686,20 +701,22 @@ AdjFn pick_adj_pair(int cpl, int depth)
 
 }  // namespace
 
-hipError_t launch_adjoint_pair(const float *in, float *out, const float *even_states,
+hipError_t launch_adjoint_pair(const AdjPlanes &io, const float *even_states, int every,
                                long long t_top, int R, int C, int bc, const Gene &g,
                                const StreamGeom &geom, double *partial, bool lam_sums,
                                hipStream_t s)
 {
     AdjFn f = lam_sums ? pick_adj_pair<true>(geom.cpl, geom.depth)
                        : pick_adj_pair<false>(geom.cpl, geom.depth);
-    if (!f || (t_top & 1) || t_top < geom.depth) return hipErrorInvalidValue;
+    if (!f || (t_top & 1) || t_top < geom.depth || every < 1) return hipErrorInvalidValue;
     AdjArgs a;
     a.t = tile_args(R, C, bc, geom);
-    a.in = in;
-    a.out = out;
-    a.states = even_states + (t_top - geom.depth) / 2 * 2LL * R * C;
-    a.state_stride = 8u * (unsigned)R * (unsigned)C;
+    a.in_l = io.in_l;
+    a.in_m = io.in_m;
+    a.out_l = io.out_l;
+    a.out_m = io.out_m;
+    a.states = even_states + (t_top - geom.depth) / 2 * every * 2LL * R * C;
+    a.state_stride = 8u * (unsigned)every * (unsigned)R * (unsigned)C;
     a.g = g;
     a.partial = partial;
     hipLaunchKernelGGL(f, dim3((unsigned)(8 * geom.per_xcd)), dim3(64), 0, s, a);
@@ -776,6 +793,12 @@ hipError_t launch_batch_adjoint_finish(const double *partial, const int *first, 
 {
     hipLaunchKernelGGL(batch_adjoint_finish_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                        s, partial, first, tiles_of, insts, n, mask, dtheta);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_row_sum(const double *rows, int n, double *dtheta, hipStream_t s)
+{
+    hipLaunchKernelGGL(grad_row_sum_kernel, dim3(1), dim3(64), 0, s, rows, n, dtheta);
     return hipGetLastError();
 }
 

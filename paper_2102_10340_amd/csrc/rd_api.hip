@@ -31,6 +31,8 @@ struct rdcnn_sim {
     int partial_device;                    // device it lives on
     int model;                             // rd::MODEL_*; g holds the FHN gene
     float mparams[rd::kModelParams];       // parameters of the other models
+    int check_finite;                      // rdcnn_read checks the state for NaN / Inf
+    int *finite_flag;                      // device counter of that check (made on first use)
 };
 
 namespace {
@@ -146,6 +148,28 @@ int ensure_partial(rdcnn_sim *h, long long need, const char *who)
     return RDCNN_OK;
 }
 
+}  // namespace
+
+int rd::check_finite_state(const float *x, long long n, int **flag, hipStream_t s, const char *who)
+{
+    if (!*flag) {
+        hipError_t e = hipMalloc((void **)flag, 256);
+        if (e != hipSuccess) {
+            *flag = nullptr;
+            return fail(RDCNN_ENOMEM, "%s: finite-check counter: %s", who, hipGetErrorString(e));
+        }
+    }
+    int bad = 0;
+    hipError_t e = rd::launch_count_nonfinite(x, n, *flag, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, *flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    if (bad) return fail(RDCNN_ENONFINITE, "%s: %d non-finite values in the state", who, bad);
+    return RDCNN_OK;
+}
+
+namespace {
+
 bool finite_params(const rdcnn_params_t *p)
 {
     const float v[8] = {p->dt, p->a, p->b, p->eps, p->c, p->k3, p->Du, p->Dv};
@@ -167,6 +191,26 @@ rd::Gene to_gene(const rdcnn_params_t *p)
     g.Dv = p->Dv;
     return g;
 }
+
+// The (lam, mu) planes of a chain of reverse passes: each pass reads one pair
+// and writes the other; copy_back leaves the result in the first pair.
+struct Pingpong {
+    float *p[2][2];  // [pair][lam, mu]
+    int cur = 0;
+    Pingpong(float *l0, float *m0, float *l1, float *m1) : p{{l0, m0}, {l1, m1}} {}
+    rd::AdjPlanes io() const { return {p[cur][0], p[cur][1], p[1 - cur][0], p[1 - cur][1]}; }
+    void flip() { cur = 1 - cur; }
+    hipError_t copy_back(size_t n, hipStream_t s)
+    {
+        if (cur == 0) return hipSuccess;
+        hipError_t e = hipMemcpyAsync(p[0][0], p[1][0], sizeof(float) * n,
+                                      hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(p[0][1], p[1][1], sizeof(float) * n, hipMemcpyDeviceToDevice, s);
+        cur = 0;
+        return e;
+    }
+};
 
 // Default pass settings for a grid when the caller has not forced any (from
 // sweeps on MI355X: wide strips and deep passes pay off only on large grids;
@@ -238,8 +282,10 @@ int run_model_steps(rdcnn_sim *h, long long n)
 
 // Run n steps from buf[cur]; flips cur once per pass.  If rec is not null the
 // state each step starts from is also written to rec[0..n-1] (2*R*C floats
-// each); with rec_even only the states of even times, s_{2i} to rec[i].
-int run_steps(rdcnn_sim *h, long long n, float *rec, bool rec_even = false)
+// each); with rec_even only the states of even times, s_{2i} to rec[i * every]
+// (every = 1: a compact even-time trajectory; 2: the even slots of a
+// trajectory with a slot per time).
+int run_steps(rdcnn_sim *h, long long n, float *rec, bool rec_even = false, int every = 1)
 {
     if (h->model != rd::MODEL_FHN) {
         if (rec) return fail(RDCNN_EINVAL, "rdcnn_step_record: FitzHugh-Nagumo grids only");
@@ -259,9 +305,12 @@ int run_steps(rdcnn_sim *h, long long n, float *rec, bool rec_even = false)
         if (rec_even) {
             // Even-state recording: every pass but the last starts at an even
             // time, so passes of an even depth (<= 8; one or two columns per lane).
+            // A pass spans its (depth-1)/2 further recorded states, `every`
+            // slots apart, past the first.
             if (cpl > 2) cpl = 2;
             if (depth > 8) depth = 8;
-            if (depth > 2 * cap) depth = (int)(2 * cap);
+            const long long dmax = 2 * ((cap - 1) / every + 1);
+            if (depth > dmax) depth = (int)dmax;
             if (depth > 1) depth &= ~1;
         } else if (depth > cap) {
             depth = (int)cap;
@@ -277,13 +326,13 @@ int run_steps(rdcnn_sim *h, long long n, float *rec, bool rec_even = false)
         const float *in = h->buf[h->cur];
         while (n > 0) {
             const int k = (int)(n < depth ? n : depth);
-            float *out = n == k ? h->buf[1 - h->cur] : rec + (size_t)((q + k) / 2) * state;
+            float *out = n == k ? h->buf[1 - h->cur] : rec + (size_t)((q + k) / 2) * every * state;
             rd::StreamGeom geom;
             if (!rd::stream_geometry(h->R, h->C, cpl, k, seg, &geom))
                 return fail(RDCNN_EINVAL, "rdcnn_step: cannot tile %dx%d with cpl=%d depth=%d",
                             h->R, h->C, cpl, k);
             hipError_t e = rd::launch_stream(in, out, h->R, h->C, h->bc, h->g, geom, h->stream,
-                                             rec, q / 2, true, q > 0);
+                                             rec, q / 2, true, q > 0, every);
             if (e != hipSuccess) return hip_fail(e, "rdcnn_step: kernel launch");
             in = out;
             n -= k;
@@ -300,7 +349,7 @@ int run_steps(rdcnn_sim *h, long long n, float *rec, bool rec_even = false)
         if (kind == 1) {
             e = hipSuccess;
             if (rec && (!rec_even || q % 2 == 0))
-                e = hipMemcpyAsync(rec + (rec_even ? q / 2 : q) * 2LL * h->R * h->C, in,
+                e = hipMemcpyAsync(rec + (rec_even ? q / 2 * every : q) * 2LL * h->R * h->C, in,
                                    sizeof(float) * 2 * h->R * h->C, hipMemcpyDeviceToDevice,
                                    h->stream);
             if (e == hipSuccess) e = rd::launch_naive(in, out, h->R, h->C, h->bc, h->g, h->stream);
@@ -315,7 +364,7 @@ int run_steps(rdcnn_sim *h, long long n, float *rec, bool rec_even = false)
                 e = rd::launch_stream(in, out, h->R, h->C, h->bc, h->g, geom, h->stream);
             else
                 e = rd::launch_stream(in, out, h->R, h->C, h->bc, h->g, geom, h->stream, rec,
-                                      rec_even ? q / 2 : q, rec_even);
+                                      rec_even ? q / 2 : q, rec_even, false, every);
             done = k;
         }
         if (e != hipSuccess) return hip_fail(e, "rdcnn_step: kernel launch");
@@ -399,6 +448,8 @@ rdcnn_sim *new_sim(int rows, int cols, int bc, float *buf0, float *buf1, void *s
     h->partial_device = 0;
     h->model = rd::MODEL_FHN;
     for (float &x : h->mparams) x = 0.0f;
+    h->check_finite = 0;
+    h->finite_flag = nullptr;
     return h;
 }
 
@@ -563,43 +614,39 @@ int rdcnn_adjoint(rdcnn_t h, const float *states_dev, long long S, float *adj_de
     }
     hipError_t e = rd::launch_zero(h->partial, rd::kAdjSums * need, h->stream);
     if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint: zero");
-    float *cur = adj_dev, *other = adj_tmp_dev;
+    const size_t n = (size_t)h->R * h->C;
+    Pingpong pp(adj_dev, adj_dev + n, adj_tmp_dev, adj_tmp_dev + n);
     long long q_top = S - 1, left = S;
     while (left > 0) {
         const int k = (int)(left < depth ? left : depth);
         rd::StreamGeom geom;
         if (!rd::stream_geometry(h->R, h->C, cpl, k, seg, &geom))
             return fail(RDCNN_EINVAL, "rdcnn_adjoint: cannot tile %dx%d", h->R, h->C);
-        e = rd::launch_adjoint(cur, other, states_dev, q_top, h->R, h->C, h->bc, h->g, geom,
+        e = rd::launch_adjoint(pp.io(), states_dev, 1, q_top, h->R, h->C, h->bc, h->g, geom,
                                h->partial, (h->grad_mask & kLamSumGrads) != 0, h->stream);
         if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint: kernel launch");
-        float *tmp = cur;
-        cur = other;
-        other = tmp;
+        pp.flip();
         q_top -= k;
         left -= k;
     }
-    if (cur != adj_dev) {
-        e = hipMemcpyAsync(adj_dev, cur, sizeof(float) * 2 * (size_t)h->R * h->C,
-                           hipMemcpyDeviceToDevice, h->stream);
-        if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint: copy back");
-    }
+    e = pp.copy_back(n, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint: copy back");
     e = rd::launch_adjoint_finish(h->partial, (int)need, h->g, h->grad_mask, dtheta_dev, h->stream);
     if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint: finish");
     return RDCNN_OK;
 }
 
-int rdcnn_adjoint_even(rdcnn_t h, const float *states_dev, long long S, float *adj_dev,
-                       float *adj_tmp_dev, double *dtheta_dev)
+namespace {
+
+// Pass shape and partial-sum tiles of the paired reverse passes through S
+// steps, reading even states `every` slots apart.
+struct PairPlan {
+    int cpl, depth, seg;
+    long long need;  // tiles of the widest tiling
+};
+
+int plan_pairs(const rdcnn_sim *h, long long S, int every, const char *who, PairPlan *pl)
 {
-    if (!h) return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: NULL handle");
-    if (h->model != rd::MODEL_FHN)
-        return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: FitzHugh-Nagumo grids only");
-    if (S < 0) return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: S = %lld < 0", S);
-    if (!adj_dev || !adj_tmp_dev || !dtheta_dev || (S > 0 && !states_dev))
-        return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: NULL argument");
-    if (adj_dev == adj_tmp_dev) return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: adj buffers alias");
-    if (S == 0) return RDCNN_OK;
     int cpl = h->adj_cpl, depth = h->adj_depth, seg = h->adj_seg_rows;
     if (depth == 0) adj_even_auto_config(h, &cpl, &depth, &seg);
     // Paired passes: an even depth of 2..8, one or two columns per lane.
@@ -608,10 +655,12 @@ int rdcnn_adjoint_even(rdcnn_t h, const float *states_dev, long long S, float *a
     if (depth < 2) depth = 2;
     depth &= ~1;
     {
-        // A pass reads its depth/2 even states through one 4 GiB buffer resource.
+        // A pass reads its depth/2 even states, `every` slots apart, through
+        // one 4 GiB buffer resource.
         const long long cap = ((1LL << 32) - 1) / (8LL * h->R * h->C);
-        if (cap < 1) return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: grid too large");
-        if (depth > 2 * cap) depth = (int)(2 * cap);
+        if (cap < 1) return fail(RDCNN_EINVAL, "%s: grid too large", who);
+        const long long dmax = 2 * ((cap - 1) / every + 1);
+        if (depth > dmax) depth = (int)dmax;
     }
     // An odd S starts with one plain reverse step (state s_{S-1} is even);
     // then paired passes of `depth` steps and one shorter even remainder.
@@ -622,50 +671,191 @@ int rdcnn_adjoint_even(rdcnn_t h, const float *states_dev, long long S, float *a
         if (k == 0) continue;
         rd::StreamGeom gk;
         if (!rd::stream_geometry(h->R, h->C, cpl, k, seg, &gk))
-            return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: cannot tile %dx%d", h->R, h->C);
+            return fail(RDCNN_EINVAL, "%s: cannot tile %dx%d", who, h->R, h->C);
         if (gk.ntiles > need) need = gk.ntiles;
     }
-    {
-        const int rc = ensure_partial(h, need, "rdcnn_adjoint_even");
-        if (rc != RDCNN_OK) return rc;
-    }
-    hipError_t e = rd::launch_zero(h->partial, rd::kAdjSums * need, h->stream);
-    if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint_even: zero");
+    pl->cpl = cpl;
+    pl->depth = depth;
+    pl->seg = seg;
+    pl->need = need;
+    return RDCNN_OK;
+}
+
+// The paired reverse passes through S steps from an even-time trajectory
+// (state s_{t0+2i} at states + i * every states), ping-ponging (lam, mu)
+// between pp's two pairs of planes; the per-tile sums go to `partial` (need
+// tiles, zeroed here) and are folded into dtheta.
+int run_pairs(rdcnn_sim *h, const float *states, int every, long long S, Pingpong &pp,
+              const PairPlan &pl, double *partial, double *dtheta, const char *who)
+{
+    hipError_t e = rd::launch_zero(partial, rd::kAdjSums * pl.need, h->stream);
+    if (e != hipSuccess) return hip_fail(e, who);
     const bool lam_sums = (h->grad_mask & kLamSumGrads) != 0;
-    float *cur = adj_dev, *other = adj_tmp_dev;
-    auto flip = [&]() {
-        float *tmp = cur;
-        cur = other;
-        other = tmp;
-    };
+    const long long even = S & ~1LL;
     if (S & 1) {
         rd::StreamGeom geom;
-        if (!rd::stream_geometry(h->R, h->C, cpl, 1, seg, &geom))
-            return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: cannot tile %dx%d", h->R, h->C);
-        e = rd::launch_adjoint(cur, other, states_dev, (S - 1) / 2, h->R, h->C, h->bc, h->g, geom,
-                               h->partial, lam_sums, h->stream);
-        if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint_even: kernel launch");
-        flip();
+        if (!rd::stream_geometry(h->R, h->C, pl.cpl, 1, pl.seg, &geom))
+            return fail(RDCNN_EINVAL, "%s: cannot tile %dx%d", who, h->R, h->C);
+        e = rd::launch_adjoint(pp.io(), states, every, (S - 1) / 2, h->R, h->C, h->bc, h->g, geom,
+                               partial, lam_sums, h->stream);
+        if (e != hipSuccess) return hip_fail(e, who);
+        pp.flip();
     }
     for (long long t_top = even; t_top > 0;) {
-        const int k = (int)(t_top < depth ? t_top : depth);
+        const int k = (int)(t_top < pl.depth ? t_top : pl.depth);
         rd::StreamGeom geom;
-        if (!rd::stream_geometry(h->R, h->C, cpl, k, seg, &geom))
-            return fail(RDCNN_EINVAL, "rdcnn_adjoint_even: cannot tile %dx%d", h->R, h->C);
-        e = rd::launch_adjoint_pair(cur, other, states_dev, t_top, h->R, h->C, h->bc, h->g, geom,
-                                    h->partial, lam_sums, h->stream);
-        if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint_even: kernel launch");
-        flip();
+        if (!rd::stream_geometry(h->R, h->C, pl.cpl, k, pl.seg, &geom))
+            return fail(RDCNN_EINVAL, "%s: cannot tile %dx%d", who, h->R, h->C);
+        e = rd::launch_adjoint_pair(pp.io(), states, every, t_top, h->R, h->C, h->bc, h->g, geom,
+                                    partial, lam_sums, h->stream);
+        if (e != hipSuccess) return hip_fail(e, who);
+        pp.flip();
         t_top -= k;
     }
-    if (cur != adj_dev) {
-        e = hipMemcpyAsync(adj_dev, cur, sizeof(float) * 2 * (size_t)h->R * h->C,
-                           hipMemcpyDeviceToDevice, h->stream);
-        if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint_even: copy back");
-    }
-    e = rd::launch_adjoint_finish(h->partial, (int)need, h->g, h->grad_mask, dtheta_dev, h->stream);
-    if (e != hipSuccess) return hip_fail(e, "rdcnn_adjoint_even: finish");
+    e = pp.copy_back((size_t)h->R * h->C, h->stream);
+    if (e != hipSuccess) return hip_fail(e, who);
+    e = rd::launch_adjoint_finish(partial, (int)pl.need, h->g, h->grad_mask, dtheta, h->stream);
+    if (e != hipSuccess) return hip_fail(e, who);
     return RDCNN_OK;
+}
+
+// Checks shared by the reverse-pass entry points; fills *done when S == 0.
+int check_bwd(const rdcnn_sim *h, long long S, const void *states, const void *a, const void *b,
+              const void *dtheta, const char *who)
+{
+    if (!h) return fail(RDCNN_EINVAL, "%s: NULL handle", who);
+    if (h->model != rd::MODEL_FHN) return fail(RDCNN_EINVAL, "%s: FitzHugh-Nagumo grids only", who);
+    if (S < 0) return fail(RDCNN_EINVAL, "%s: S = %lld < 0", who, S);
+    if (!a || !b || !dtheta || (S > 0 && !states)) return fail(RDCNN_EINVAL, "%s: NULL argument", who);
+    if (a == b) return fail(RDCNN_EINVAL, "%s: buffers alias", who);
+    return RDCNN_OK;
+}
+
+// rdcnn_step_bwd's buffers: lam and mu are distinct planes, and the workspace
+// slot S of the trajectory overlaps neither.
+int check_step_bwd(const rdcnn_sim *h, const float *states, long long S, const float *lam,
+                   const float *mu, const char *who)
+{
+    const size_t n = (size_t)h->R * h->C;
+    const char *l0 = (const char *)lam, *m0 = (const char *)mu;
+    const char *w0 = (const char *)(states + (size_t)S * 2 * n);
+    const size_t pb = sizeof(float) * n;
+    auto overlap = [](const char *x, size_t nx, const char *y, size_t ny) {
+        return x < y + ny && y < x + nx;
+    };
+    if (overlap(l0, pb, m0, pb)) return fail(RDCNN_EINVAL, "%s: lam and mu overlap", who);
+    if (overlap(w0, 2 * pb, l0, pb) || overlap(w0, 2 * pb, m0, pb))
+        return fail(RDCNN_EINVAL, "%s: lam or mu overlaps the trajectory's workspace slot S", who);
+    return RDCNN_OK;
+}
+
+}  // namespace
+
+int rdcnn_adjoint_even(rdcnn_t h, const float *states_dev, long long S, float *adj_dev,
+                       float *adj_tmp_dev, double *dtheta_dev)
+{
+    const char *who = "rdcnn_adjoint_even";
+    int rc = check_bwd(h, S, states_dev, adj_dev, adj_tmp_dev, dtheta_dev, who);
+    if (rc != RDCNN_OK || S == 0) return rc;
+    PairPlan pl;
+    if ((rc = plan_pairs(h, S, 1, who, &pl)) != RDCNN_OK) return rc;
+    if ((rc = ensure_partial(h, pl.need, who)) != RDCNN_OK) return rc;
+    const size_t n = (size_t)h->R * h->C;
+    Pingpong pp(adj_dev, adj_dev + n, adj_tmp_dev, adj_tmp_dev + n);
+    return run_pairs(h, states_dev, 1, S, pp, pl, h->partial, dtheta_dev, who);
+}
+
+int rdcnn_step_record_sparse(rdcnn_t h, long long T, float *states_dev)
+{
+    if (!h) return fail(RDCNN_EINVAL, "rdcnn_step_record_sparse: NULL handle");
+    if (T < 0) return fail(RDCNN_EINVAL, "rdcnn_step_record_sparse: T = %lld < 0", T);
+    if (T > 0 && !states_dev)
+        return fail(RDCNN_EINVAL, "rdcnn_step_record_sparse: NULL states buffer");
+    if (T > 0) {
+        // the passes read their input from the trajectory's even slots: they
+        // must not overlap the handle's state buffers
+        const size_t state = 2 * (size_t)h->R * h->C;
+        const char *t0 = (const char *)states_dev;
+        const char *t1 = t0 + sizeof(float) * state * (size_t)(T + 1);
+        for (float *b : h->buf) {
+            const char *b0 = (const char *)b, *b1 = b0 + sizeof(float) * state;
+            if (t0 < b1 && b0 < t1)
+                return fail(RDCNN_EINVAL, "rdcnn_step_record_sparse: states buffer overlaps a "
+                                          "state buffer of the handle");
+        }
+    }
+    return run_steps(h, T, states_dev, true, 2);
+}
+
+int rdcnn_step_checkpoints(rdcnn_t h, long long T, long long S, float *ckpt_dev)
+{
+    const char *who = "rdcnn_step_checkpoints";
+    if (!h) return fail(RDCNN_EINVAL, "%s: NULL handle", who);
+    if (T < 0 || S < 1) return fail(RDCNN_EINVAL, "%s: T = %lld, S = %lld", who, T, S);
+    if (T == 0) return RDCNN_OK;
+    if (!ckpt_dev) return fail(RDCNN_EINVAL, "%s: NULL checkpoint buffer", who);
+    if (h->model != rd::MODEL_FHN) return fail(RDCNN_EINVAL, "%s: FitzHugh-Nagumo grids only", who);
+    const size_t state = 2 * (size_t)h->R * h->C;
+    const long long nseg = (T + S - 1) / S;
+    {
+        const char *c0 = (const char *)ckpt_dev, *c1 = c0 + sizeof(float) * state * (size_t)nseg;
+        for (float *b : h->buf) {
+            const char *b0 = (const char *)b, *b1 = b0 + sizeof(float) * state;
+            if (c0 < b1 && b0 < c1)
+                return fail(RDCNN_EINVAL, "%s: checkpoint buffer overlaps a state buffer", who);
+        }
+    }
+    int kind = h->kind, cpl = h->cpl, depth = h->depth, seg = h->seg_rows;
+    if (kind == 0) {
+        kind = 2;
+        auto_config(h, &cpl, &depth, &seg, false);
+    }
+    hipError_t e = hipMemcpyAsync(ckpt_dev, h->buf[h->cur], sizeof(float) * state,
+                                  hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(e, who);
+    // Passes stop at every multiple of S; the pass that ends at jS < T writes
+    // its output straight into checkpoint j and the next pass reads it there.
+    const float *in = h->buf[h->cur];
+    for (long long q = 0; q < T;) {
+        const long long bound = (q / S + 1) * S;
+        long long k = kind == 1 ? 1 : depth;
+        if (k > T - q) k = T - q;
+        if (k > bound - q) k = bound - q;
+        const long long end = q + k;
+        float *out = end % S == 0 && end < T ? ckpt_dev + (size_t)(end / S) * state
+                     : in == h->buf[0]      ? h->buf[1]
+                                            : h->buf[0];
+        if (kind == 1) {
+            e = rd::launch_naive(in, out, h->R, h->C, h->bc, h->g, h->stream);
+        } else {
+            rd::StreamGeom geom;
+            if (!rd::stream_geometry(h->R, h->C, cpl, (int)k, seg, &geom))
+                return fail(RDCNN_EINVAL, "%s: cannot tile %dx%d with cpl=%d depth=%lld", who, h->R,
+                            h->C, cpl, k);
+            e = rd::launch_stream(in, out, h->R, h->C, h->bc, h->g, geom, h->stream);
+        }
+        if (e != hipSuccess) return hip_fail(e, who);
+        in = out;
+        q = end;
+    }
+    h->cur = in == h->buf[0] ? 0 : 1;
+    return RDCNN_OK;
+}
+
+int rdcnn_step_bwd(rdcnn_t h, float *states_dev, long long S, float *lam_dev, float *mu_dev,
+                   double *dtheta_accum)
+{
+    const char *who = "rdcnn_step_bwd";
+    int rc = check_bwd(h, S, states_dev, lam_dev, mu_dev, dtheta_accum, who);
+    if (rc != RDCNN_OK || S == 0) return rc;
+    if ((rc = check_step_bwd(h, states_dev, S, lam_dev, mu_dev, who)) != RDCNN_OK) return rc;
+    PairPlan pl;
+    if ((rc = plan_pairs(h, S, 2, who, &pl)) != RDCNN_OK) return rc;
+    if ((rc = ensure_partial(h, pl.need, who)) != RDCNN_OK) return rc;
+    const size_t n = (size_t)h->R * h->C;
+    float *work = states_dev + (size_t)S * 2 * n;  // slot S: never read as a state
+    Pingpong pp(lam_dev, mu_dev, work, work + n);
+    return run_pairs(h, states_dev, 2, S, pp, pl, h->partial, dtheta_accum, who);
 }
 
 int rdcnn_set_grad_mask(rdcnn_t h, unsigned mask)
@@ -694,8 +884,17 @@ int rdcnn_read(rdcnn_t h, float *u_dst, float *v_dst, int dst_is_host)
     const hipMemcpyKind kind = dst_is_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     hipError_t e = hipMemcpyAsync(u_dst, s, bytes, kind, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(v_dst, s + (size_t)h->R * h->C, bytes, kind, h->stream);
-    if (e == hipSuccess && dst_is_host) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess && dst_is_host && !h->check_finite) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "rdcnn_read");
+    if (h->check_finite)
+        return rd::check_finite_state(s, 2LL * h->R * h->C, &h->finite_flag, h->stream, "rdcnn_read");
+    return RDCNN_OK;
+}
+
+int rdcnn_set_check_finite(rdcnn_t h, int on)
+{
+    if (!h) return fail(RDCNN_EINVAL, "rdcnn_set_check_finite: NULL handle");
+    h->check_finite = on != 0;
     return RDCNN_OK;
 }
 
@@ -749,10 +948,44 @@ int rdcnn_set_kernel(rdcnn_t h, int kind, int depth, int cols_per_lane, int seg_
     return RDCNN_OK;
 }
 
+int rdcnn_pass_config(rdcnn_t h, int *kind, int *depth, int *cols_per_lane, int *seg_rows)
+{
+    if (!h || !kind || !depth || !cols_per_lane || !seg_rows)
+        return fail(RDCNN_EINVAL, "rdcnn_pass_config: NULL argument");
+    int k = h->kind, cpl = h->cpl, d = h->depth, seg = h->seg_rows;
+    if (h->model != rd::MODEL_FHN) {
+        if (k == 0) {
+            k = 2;
+            cpl = h->R >= 2048 && h->C >= 2048 ? 2 : 1;
+            d = 8;
+            seg = 0;
+        }
+        if (cpl > 2) cpl = 2;
+    } else if (k == 0) {
+        k = 2;
+        auto_config(h, &cpl, &d, &seg, false);
+    }
+    if (k == 1) {
+        cpl = d = 1;
+        seg = 1;
+    } else {
+        rd::StreamGeom geom;
+        if (!rd::stream_geometry(h->R, h->C, cpl, d, seg, &geom))
+            return fail(RDCNN_EINVAL, "rdcnn_pass_config: cannot tile %dx%d", h->R, h->C);
+        seg = geom.h;
+    }
+    *kind = k;
+    *depth = d;
+    *cols_per_lane = cpl;
+    *seg_rows = seg;
+    return RDCNN_OK;
+}
+
 int rdcnn_destroy(rdcnn_t h)
 {
     if (!h) return RDCNN_OK;
     pool_put(h->partial_device, h->partial_cap, h->partial, h->stream);
+    if (h->finite_flag) (void)hipFree(h->finite_flag);
     delete h;
     return RDCNN_OK;
 }

@@ -295,6 +295,10 @@ struct rdcnn_batch {
     int adj_cpl, adj_depth, adj_seg;
     int *adj_first, *adj_tiles_of;
     double *adj_partial;
+    int shared_grad;     // dtheta is one gradient of parameters shared by all instances
+    double *grad_rows;   // per-instance rows summed into it (made on first use)
+    int check_finite;    // rdcnn_batch_read checks the state for NaN / Inf
+    int *finite_flag;    // device counter of that check (made on first use)
 };
 
 #define bfail(...) rd::set_error(__VA_ARGS__)
@@ -495,6 +499,31 @@ void free_adj(rdcnn_batch *b)
     b->adj_table = TileTable();
     b->adj_first = b->adj_tiles_of = nullptr;
     b->adj_partial = nullptr;
+    if (b->grad_rows) (void)hipFree(b->grad_rows);
+    b->grad_rows = nullptr;
+}
+
+// Fold the per-tile partials into the gradients: one row of 8 per instance
+// added to dtheta, or with shared parameters the rows summed over instances
+// in index order and added to dtheta[0 .. 8).
+hipError_t finish_grads(rdcnn_batch *b, unsigned mask, double *dtheta)
+{
+    if (!b->shared_grad)
+        return rd::launch_batch_adjoint_finish(b->adj_partial, b->adj_first, b->adj_tiles_of,
+                                               b->insts_dev, b->n, mask, dtheta, b->stream);
+    if (!b->grad_rows) {
+        hipError_t e = hipMalloc((void **)&b->grad_rows, sizeof(double) * 8 * (size_t)b->n);
+        if (e != hipSuccess) {
+            b->grad_rows = nullptr;
+            return e;
+        }
+    }
+    hipError_t e = rd::launch_zero(b->grad_rows, 8LL * b->n, b->stream);
+    if (e == hipSuccess)
+        e = rd::launch_batch_adjoint_finish(b->adj_partial, b->adj_first, b->adj_tiles_of,
+                                            b->insts_dev, b->n, mask, b->grad_rows, b->stream);
+    if (e == hipSuccess) e = rd::launch_grad_row_sum(b->grad_rows, b->n, dtheta, b->stream);
+    return e;
 }
 
 // The reverse pass's tile list (every instance, cut for adj_depth), its
@@ -662,6 +691,10 @@ int rdcnn_batch_create(rdcnn_batch_t *out, int n, const int *rows, const int *co
     b->adj_seg = 128;
     b->adj_first = b->adj_tiles_of = nullptr;
     b->adj_partial = nullptr;
+    b->shared_grad = 0;
+    b->grad_rows = nullptr;
+    b->check_finite = 0;
+    b->finite_flag = nullptr;
     b->use_lds = 1;
     b->lds_ids_dev = nullptr;
     b->lds_count = b->lds_frame = 0;
@@ -868,9 +901,7 @@ int rdcnn_batch_adjoint(rdcnn_batch_t b, const float *traj, long long S, float *
     }
     if (e == hipSuccess && src != adj)
         e = hipMemcpyAsync(adj, src, sizeof(float) * b->total, hipMemcpyDeviceToDevice, b->stream);
-    if (e == hipSuccess)
-        e = rd::launch_batch_adjoint_finish(b->adj_partial, b->adj_first, b->adj_tiles_of,
-                                            b->insts_dev, b->n, mask, dtheta, b->stream);
+    if (e == hipSuccess) e = finish_grads(b, mask, dtheta);
     if (e != hipSuccess) return bfail(RDCNN_EHIP, "rdcnn_batch_adjoint: %s", hipGetErrorString(e));
     return RDCNN_OK;
 }
@@ -925,9 +956,7 @@ int rdcnn_batch_adjoint_even(rdcnn_batch_t b, const float *traj, long long S, fl
     }
     if (e == hipSuccess && src != adj)
         e = hipMemcpyAsync(adj, src, sizeof(float) * b->total, hipMemcpyDeviceToDevice, b->stream);
-    if (e == hipSuccess)
-        e = rd::launch_batch_adjoint_finish(b->adj_partial, b->adj_first, b->adj_tiles_of,
-                                            b->insts_dev, b->n, mask, dtheta, b->stream);
+    if (e == hipSuccess) e = finish_grads(b, mask, dtheta);
     if (e != hipSuccess)
         return bfail(RDCNN_EHIP, "rdcnn_batch_adjoint_even: %s", hipGetErrorString(e));
     return RDCNN_OK;
@@ -1051,6 +1080,41 @@ int rdcnn_batch_current(rdcnn_batch_t b, float **state_dev)
     return RDCNN_OK;
 }
 
+int rdcnn_batch_read(rdcnn_batch_t b, float *dst_packed_dev)
+{
+    if (!b || !dst_packed_dev) return bfail(RDCNN_EINVAL, "rdcnn_batch_read: NULL argument");
+    const float *src = b->buf[b->cur];
+    const char *d0 = (const char *)dst_packed_dev, *s0 = (const char *)src;
+    const size_t bytes = sizeof(float) * (size_t)b->total;
+    if (d0 < s0 + bytes && s0 < d0 + bytes)
+        return bfail(RDCNN_EINVAL, "rdcnn_batch_read: destination overlaps the current state");
+    hipError_t e = hipMemcpyAsync(dst_packed_dev, src, bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e != hipSuccess) return bfail(RDCNN_EHIP, "rdcnn_batch_read: %s", hipGetErrorString(e));
+    if (b->check_finite) {
+        // only the instances' cells: padding between them is not state
+        for (int i = 0; i < b->n; ++i) {
+            const int rc = rd::check_finite_state(src + b->off[i], 2LL * b->R[i] * b->C[i],
+                                                  &b->finite_flag, b->stream, "rdcnn_batch_read");
+            if (rc != RDCNN_OK) return rc;
+        }
+    }
+    return RDCNN_OK;
+}
+
+int rdcnn_batch_set_check_finite(rdcnn_batch_t b, int on)
+{
+    if (!b) return bfail(RDCNN_EINVAL, "rdcnn_batch_set_check_finite: NULL handle");
+    b->check_finite = on != 0;
+    return RDCNN_OK;
+}
+
+int rdcnn_batch_set_shared_grad(rdcnn_batch_t b, int on)
+{
+    if (!b) return bfail(RDCNN_EINVAL, "rdcnn_batch_set_shared_grad: NULL handle");
+    b->shared_grad = on != 0;
+    return RDCNN_OK;
+}
+
 int rdcnn_batch_destroy(rdcnn_batch_t b)
 {
     if (!b) return RDCNN_OK;
@@ -1059,6 +1123,7 @@ int rdcnn_batch_destroy(rdcnn_batch_t b)
     free_lds(b);
     free_stats(b);
     free_adj(b);
+    if (b->finite_flag) (void)hipFree(b->finite_flag);
     if (b->insts_dev) (void)hipFree(b->insts_dev);
     delete b;
     return RDCNN_OK;

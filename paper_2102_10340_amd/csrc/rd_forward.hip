@@ -45,6 +45,33 @@ hipError_t launch_init(const float *x, float ka, float *state, long long n, hipS
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- finite check
+
+__global__ __launch_bounds__(256) void fill_int_kernel(int *p, int v) { p[threadIdx.x] = v; }
+
+// Adds the number of NaN or infinite values among x[0 .. n) to *count.  The
+// count is an integer, so the order of the atomic adds does not matter.
+__global__ __launch_bounds__(256) void count_nonfinite_kernel(const float *__restrict__ x,
+                                                              long long n, int *count)
+{
+    int bad = 0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        bad += !__builtin_isfinite(x[i]);
+    if (bad) atomicAdd(count, bad);
+}
+
+hipError_t launch_count_nonfinite(const float *x, long long n, int *count, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, s, count, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n <= 0) return e;
+    long long blocks = (n + 1023) / 1024;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(count_nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, count);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- naive
 
 __global__ __launch_bounds__(256) void naive_step_kernel(const float *__restrict__ in,
@@ -173,8 +200,9 @@ TileArgs tile_args(int R, int C, int bc, const StreamGeom &geom)
 
 hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, const Gene &g,
                          const StreamGeom &geom, hipStream_t s, float *rec, long long rec_q0,
-                         bool rec_even, bool skip_level0)
+                         bool rec_even, bool skip_level0, int rec_every)
 {
+    if (rec_every < 1) return hipErrorInvalidValue;
     StreamFn f = !rec ? pick_stream<0>(geom.cpl, geom.depth)
                  : !rec_even ? pick_stream<1>(geom.cpl, geom.depth)
                  : skip_level0 ? pick_stream<3>(geom.cpl, geom.depth)
@@ -185,8 +213,8 @@ hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, cons
     a.in = in;
     a.out = out;
     a.g = g;
-    a.rec = rec ? rec + rec_q0 * 2LL * R * C : nullptr;
-    a.rec_stride = 8u * (unsigned)R * (unsigned)C;
+    a.rec = rec ? rec + rec_q0 * rec_every * 2LL * R * C : nullptr;
+    a.rec_stride = 8u * (unsigned)rec_every * (unsigned)R * (unsigned)C;
     hipLaunchKernelGGL(f, dim3((unsigned)(8 * geom.per_xcd)), dim3(64), 0, s, a);
     return hipGetLastError();
 }

@@ -9,6 +9,12 @@ namespace rd {
 // Record a message for rdcnn_last_error() (thread-local) and return `code`.
 int set_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 
+// Finite check of a state on the host's request: counts the NaN or infinite
+// values among x[0 .. n) on the stream, waits for it, and returns
+// RDCNN_ENONFINITE (with a message) if there are any, else RDCNN_OK.  *flag
+// is a small device counter made on first use (freed by the caller).
+int check_finite_state(const float *x, long long n, int **flag, hipStream_t s, const char *who);
+
 // Largest number of time steps one register-streamed pass may take, per
 // columns-per-lane setting (bounded by the 256 architected VGPRs a wave has).
 constexpr int kMaxDepthCpl1 = 16;
@@ -63,9 +69,12 @@ hipError_t launch_naive(const float *in, float *out, int R, int C, int bc, const
 // rec + (rec_q0 + j/2) * 2*R*C (the pass must start at an even time; cpl 1 or
 // 2, depth <= 8), and with skip_level0 too the even levels from 2 on (`in` is
 // already recorded state rec_q0).
+// rec_every spaces recorded states rec_every states apart (2: even-time states
+// into the even slots of a trajectory with a slot per time).
 hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, const Gene &g,
                          const StreamGeom &geom, hipStream_t s, float *rec = nullptr,
-                         long long rec_q0 = 0, bool rec_even = false, bool skip_level0 = false);
+                         long long rec_q0 = 0, bool rec_even = false, bool skip_level0 = false,
+                         int rec_every = 1);
 
 // Cell models other than FitzHugh-Nagumo on the same streamed kernel
 // (rd_models.h).  Their passes take depth 1, 2, 4 or 8 and cols_per_lane 1 or 2.
@@ -83,21 +92,38 @@ hipError_t launch_model(int model, const float *in, float *out, int R, int C, in
 hipError_t launch_cnn_input(const float *img, const float *bz, int R, int C, int bc, float *w,
                             hipStream_t s);
 
-// `geom.depth` reverse steps: (lam, mu) `in` -> `out`, reading states
-// states[q_top], states[q_top-1], ...; adds each tile's eight sums to partial.
+// The (lam, mu) planes a reverse pass reads (in) and writes (out), R x C each.
+struct AdjPlanes {
+    const float *in_l, *in_m;
+    float *out_l, *out_m;
+};
+
+// `geom.depth` reverse steps: (lam, mu) io.in -> io.out, reading states
+// q_top, q_top-1, ... of a trajectory whose state q sits at states + q *
+// every * 2*R*C floats; adds each tile's eight sums to partial.
 // lam_sums: also form the sums only dJ/ddt, dJ/dc and dJ/dk3 need.
-hipError_t launch_adjoint(const float *in, float *out, const float *states, long long q_top,
+hipError_t launch_adjoint(const AdjPlanes &io, const float *states, int every, long long q_top,
                           int R, int C, int bc, const Gene &g, const StreamGeom &geom,
                           double *partial, bool lam_sums, hipStream_t s);
 // A paired pass: `geom.depth` (2, 4, 6 or 8; cpl 1 or 2) reverse steps from the
-// even time t_top, reading the even-time trajectory even_states (state s_{2i}
-// at index i) and rebuilding the odd states it needs.
-hipError_t launch_adjoint_pair(const float *in, float *out, const float *even_states,
+// even time t_top, reading the even-time states (s_{2i} at even_states + i *
+// every * 2*R*C floats: every = 1 for a compact even-time trajectory, 2 for
+// the even slots of a trajectory with a slot per time) and rebuilding the odd
+// states it needs.
+hipError_t launch_adjoint_pair(const AdjPlanes &io, const float *even_states, int every,
                                long long t_top, int R, int C, int bc, const Gene &g,
                                const StreamGeom &geom, double *partial, bool lam_sums,
                                hipStream_t s);
 
 hipError_t launch_zero(double *p, long long n, hipStream_t s);
+
+// *count = number of NaN or infinite values among x[0 .. n) (count is zeroed
+// first by a kernel of its own, so the launch sequence can be captured).
+hipError_t launch_count_nonfinite(const float *x, long long n, int *count, hipStream_t s);
+
+// Shared parameters of a batch: dtheta[q] += sum of rows[8 i + q] over
+// instances i = 0 .. n-1 in index order (deterministic).
+hipError_t launch_grad_row_sum(const double *rows, int n, double *dtheta, hipStream_t s);
 
 // Fold ntiles rows of partial sums into the eight gradients, added to dtheta
 // for the bits of mask (dt, a, b, eps, c, k3, Du, Dv = bits 0..7); NaN elsewhere.

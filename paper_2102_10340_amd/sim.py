@@ -12,7 +12,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import BC, Params, check, lib
+from ._lib import BC, PARAM_FIELDS, Params, check, lib
 
 
 def _stream_handle(device) -> int:
@@ -36,6 +36,7 @@ class Simulation:
                     for _ in range(2)]
         self._h = ctypes.c_void_p()
         self._params = Params.from_mapping(gene)
+        self._kernel = (0, 0, 0, 0)
         with torch.cuda.device(self.device):
             check(lib.rdcnn_create(ctypes.byref(self._h), self.rows, self.cols, BC[bc],
                                    ctypes.byref(self._params), self._x.data_ptr(), float(ka),
@@ -59,6 +60,7 @@ class Simulation:
         sim.buf = [torch.empty((2, sim.rows, sim.cols), dtype=torch.float32, device=sim.device)
                    for _ in range(2)]
         sim._h = ctypes.c_void_p()
+        sim._kernel = (0, 0, 0, 0)
         p = (ctypes.c_float * len(params))(*[float(x) for x in params])
         with torch.cuda.device(sim.device):
             check(lib.rdcnn_model_create(ctypes.byref(sim._h), cls.MODELS[name], sim.rows, sim.cols,
@@ -109,6 +111,44 @@ class Simulation:
         check(lib.rdcnn_step_record_even(self._h, int(T), states.data_ptr() if T > 0 else None))
         return self
 
+    def step_record_sparse(self, T: int, states: torch.Tensor) -> "Simulation":
+        """Advance by T steps writing the even-time states into their own slots
+        of a trajectory with one slot per time: s_{2i} to states[2i] (shape
+        [>= T+1, 2, R, C]); the layout step_bwd reads."""
+        if T > 0:
+            self._check_states(states, T + 1)
+        check(lib.rdcnn_step_record_sparse(self._h, int(T), states.data_ptr() if T > 0 else None))
+        return self
+
+    def step_checkpoints(self, T: int, S: int, ckpt: torch.Tensor) -> "Simulation":
+        """Advance by T steps keeping s_{jS} in ckpt[j] for jS < T (shape
+        [>= ceil(T/S), 2, R, C]); each checkpoint is written by the pass that
+        ends there."""
+        if T > 0:
+            self._check_states(ckpt, -(-int(T) // int(S)))
+        check(lib.rdcnn_step_checkpoints(self._h, int(T), int(S), ckpt.data_ptr() if T > 0 else None))
+        return self
+
+    def step_bwd(self, states: torch.Tensor, S: int, lam: torch.Tensor, mu: torch.Tensor,
+                 dtheta: torch.Tensor) -> None:
+        """rdcnn_step_bwd: reverse pass through the S steps whose start states
+        sit in states[q] (the even q are read; states[S] is workspace).  lam, mu
+        ([R, C] each) go from dJ/d(u, v) after the steps to before them; dJ/dp
+        (float64 [8]) is added to dtheta."""
+        if S > 0:
+            self._check_states(states, S + 1)
+        for t in (lam, mu):
+            if t.shape != (self.rows, self.cols) or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError("lam and mu must be contiguous float32 [R, C]")
+        if dtheta.dtype != torch.float64 or dtheta.numel() != 8 or not dtheta.is_cuda:
+            raise ValueError("dtheta must be a CUDA float64 tensor of 8 elements")
+        check(lib.rdcnn_step_bwd(self._h, states.data_ptr() if S > 0 else None, int(S),
+                                 lam.data_ptr(), mu.data_ptr(), dtheta.data_ptr()))
+
+    def set_check_finite(self, on: bool = True) -> None:
+        """Reads check the state for NaN / Inf and raise (RDCNN_ENONFINITE)."""
+        check(lib.rdcnn_set_check_finite(self._h, 1 if on else 0))
+
     def adjoint(self, states: torch.Tensor, S: int, adj: torch.Tensor, adj_tmp: torch.Tensor,
                 dtheta: torch.Tensor) -> None:
         """Reverse pass through S steps recorded in states[0..S-1]: adj [2, R, C]
@@ -150,6 +190,15 @@ class Simulation:
                 or states.shape[0] < n or tuple(states.shape[1:]) != (2, self.rows, self.cols)):
             raise ValueError("states must be contiguous float32 [>= n, 2, R, C]")
 
+    @property
+    def gene(self) -> dict:
+        """The current parameters (dt, a, b, eps, c, k3, Du, Dv) as floats."""
+        return {k: float(getattr(self._params, k)) for k in PARAM_FIELDS}
+
+    def kernel_setting(self):
+        """The arguments of the last set_kernel call ((0, 0, 0, 0): automatic)."""
+        return self._kernel
+
     def set_params(self, gene) -> None:
         self._params = Params.from_mapping(gene)
         check(lib.rdcnn_set_params(self._h, ctypes.byref(self._params)))
@@ -160,6 +209,13 @@ class Simulation:
         with `depth` steps per pass (bit-identical results for every choice)."""
         check(lib.rdcnn_set_kernel(self._h, int(kind), int(depth), int(cols_per_lane),
                                    int(seg_rows)))
+        self._kernel = (int(kind), int(depth), int(cols_per_lane), int(seg_rows))
+
+    def pass_config(self) -> dict:
+        """The pass shape rdcnn_step uses now (automatic choices resolved)."""
+        v = [ctypes.c_int() for _ in range(4)]
+        check(lib.rdcnn_pass_config(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("kind", "depth", "cols_per_lane", "seg_rows"), [x.value for x in v]))
 
     # -- state -----------------------------------------------------------
     def state(self) -> torch.Tensor:

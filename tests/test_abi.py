@@ -103,7 +103,25 @@ def test_null_handle_calls_fail_cleanly(L):
     assert L.lib.rdcnn_adjoint_even(None, 0x1000, 4, 0x2000, 0x3000, 0x4000) == L.EINVAL
     assert L.lib.rdcnn_batch_step_record_even(None, 4, 0x1000) == L.EINVAL
     assert L.lib.rdcnn_batch_adjoint_even(None, 0x1000, 4, 0x2000, 0x3000, 0xFF, 0x4000) == L.EINVAL
+    assert L.lib.rdcnn_step_bwd(None, 0x1000, 4, 0x2000, 0x3000, 0x4000) == L.EINVAL
+    assert L.lib.rdcnn_step_record_sparse(None, 4, 0x1000) == L.EINVAL
+    assert L.lib.rdcnn_step_checkpoints(None, 4, 2, 0x1000) == L.EINVAL
+    assert L.lib.rdcnn_set_check_finite(None, 1) == L.EINVAL
+    assert L.lib.rdcnn_batch_read(None, 0x1000) == L.EINVAL
+    assert L.lib.rdcnn_batch_set_check_finite(None, 1) == L.EINVAL
+    assert L.lib.rdcnn_batch_set_shared_grad(None, 1) == L.EINVAL
+    v = ctypes.c_int()
+    assert L.lib.rdcnn_pass_config(None, ctypes.byref(v), ctypes.byref(v), ctypes.byref(v),
+                                   ctypes.byref(v)) == L.EINVAL
     assert "NULL" in L.last_error()
+
+
+def test_status_codes_match_header(L):
+    """The Python constants are the header's enum values."""
+    text = open(os.path.join(ROOT, "include", "rdcnn.h")).read()
+    for name in ("OK", "EINVAL", "EHIP", "ENONFINITE", "ESTATE", "ENOMEM"):
+        m = re.search(r"RDCNN_%s\s*=\s*(-?\d+)" % name, text)
+        assert m and int(m.group(1)) == getattr(L, name), name
 
 
 def test_error_is_raised_as_exception(L):
