@@ -302,6 +302,27 @@ int rdcnn_step_bwd(rdcnn_t h, float *states_dev, long long S, float *lam_dev, fl
                    double *dtheta_accum);
 
 /*
+ * rdcnn_step_bwd_noalloc -- rdcnn_step_bwd for callers that cannot allocate
+ * device memory: code being captured into a HIP graph, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, kernels, launch order and
+ * results (bit for bit) as rdcnn_step_bwd; the per-tile partial sums live in
+ * a static device array of the library instead of the pooled buffer, so the
+ * call makes no hipMalloc, hipFree or other allocation.  Limit: the reverse
+ * passes may use at most 65536 tiles (4 MiB of partial sums; the automatic
+ * pass shape uses about 2600 on any grid up to 2^30 cells); more is rejected
+ * with RDCNN_EINVAL and a message naming the count.  The array is resolved
+ * once per device (at rdcnn_create, or at the first call on a device) and
+ * stays allocated until the process ends.  Every call on one device shares
+ * that device's array and zeroes it on the stream before use (by a kernel,
+ * no memset), so calls that overlap on one device -- on different streams or
+ * from different threads -- race; calls ordered on one stream do not.  Its
+ * contents after a call are the last call's partial sums.
+ * Errors: as rdcnn_step_bwd, plus RDCNN_EINVAL for a tiling over the limit.
+ */
+int rdcnn_step_bwd_noalloc(rdcnn_t h, float *states_dev, long long S, float *lam_dev,
+                           float *mu_dev, double *dtheta_accum);
+
+/*
  * rdcnn_set_adjoint_kernel -- pass settings for rdcnn_adjoint: `depth` reverse
  * steps per HBM pass, cols_per_lane 1 or 2 (depth 1..8) or 4 (depth 1..6), seg_rows
  * output rows per wavefront (0 = automatic).  depth = cols_per_lane = 0 restores

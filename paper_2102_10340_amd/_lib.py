@@ -61,6 +61,7 @@ _SIGS = {
     "rdcnn_step_record_sparse": [_P, _LL, _P],
     "rdcnn_step_checkpoints": [_P, _LL, _LL, _P],
     "rdcnn_step_bwd": [_P, _P, _LL, _P, _P, _P],
+    "rdcnn_step_bwd_noalloc": [_P, _P, _LL, _P, _P, _P],
     "rdcnn_set_check_finite": [_P, _I],
     "rdcnn_set_adjoint_kernel": [_P, _I, _I, _I],
     "rdcnn_init_backward": [_P, _LL, _F, _P, _P],

@@ -150,6 +150,48 @@ int ensure_partial(rdcnn_sim *h, long long need, const char *who)
 
 }  // namespace
 
+// Partial-sum workspace of rdcnn_step_bwd_noalloc: a fixed device array in
+// place of the pooled buffer, for callers that cannot allocate (HIP graph
+// capture, serving loops).  kNoAllocTiles tiles of kAdjSums doubles (4 MiB);
+// each device the library runs on holds its own copy until the process ends.
+// Host code never names the array itself (on the host its name is only a
+// stand-in for the symbol): it uses the device address that
+// hipGetSymbolAddress returns, resolved once per device below.
+constexpr long long kNoAllocTiles = 65536;
+static __device__ __align__(256) double scratch[rd::kAdjSums * kNoAllocTiles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices];  // scratch's address on each device (null: not resolved yet)
+
+// The address of `scratch` on the current device, resolved on the first call
+// for that device (rdcnn_create makes that call, so a handle's device is
+// resolved before any of its work can be captured).
+int scratch_address(double **out, const char *who)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, who);
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(RDCNN_EINVAL, "%s: device %d beyond the %d the workspace table holds", who, dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(RDCNN_EHIP, "%s: address of the static workspace: %s", who,
+                        hipGetErrorString(e));
+        g_scratch_dev[dev] = (double *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return RDCNN_OK;
+}
+
+}  // namespace
+
 int rd::check_finite_state(const float *x, long long n, int **flag, hipStream_t s, const char *who)
 {
     if (!*flag) {
@@ -469,6 +511,9 @@ int rdcnn_create(rdcnn_t *out, int rows, int cols, int bc, const rdcnn_params_t 
     if (!p || !finite_params(p)) return fail(RDCNN_EINVAL, "rdcnn_create: missing or non-finite parameters");
     if (!isfinite(ka)) return fail(RDCNN_EINVAL, "rdcnn_create: non-finite ka");
     if (!x_dev) return fail(RDCNN_EINVAL, "rdcnn_create: NULL device buffer");
+    double *ws = nullptr;  // set-up of rdcnn_step_bwd_noalloc's workspace on this device
+    const int rs = scratch_address(&ws, "rdcnn_create");
+    if (rs != RDCNN_OK) return rs;
     rdcnn_sim *h = new_sim(rows, cols, bc, buf0_dev, buf1_dev, stream);
     if (!h) return fail(RDCNN_ENOMEM, "rdcnn_create: out of host memory");
     h->g = to_gene(p);
@@ -856,6 +901,27 @@ int rdcnn_step_bwd(rdcnn_t h, float *states_dev, long long S, float *lam_dev, fl
     float *work = states_dev + (size_t)S * 2 * n;  // slot S: never read as a state
     Pingpong pp(lam_dev, mu_dev, work, work + n);
     return run_pairs(h, states_dev, 2, S, pp, pl, h->partial, dtheta_accum, who);
+}
+
+int rdcnn_step_bwd_noalloc(rdcnn_t h, float *states_dev, long long S, float *lam_dev,
+                           float *mu_dev, double *dtheta_accum)
+{
+    const char *who = "rdcnn_step_bwd_noalloc";
+    int rc = check_bwd(h, S, states_dev, lam_dev, mu_dev, dtheta_accum, who);
+    if (rc != RDCNN_OK || S == 0) return rc;
+    if ((rc = check_step_bwd(h, states_dev, S, lam_dev, mu_dev, who)) != RDCNN_OK) return rc;
+    PairPlan pl;
+    if ((rc = plan_pairs(h, S, 2, who, &pl)) != RDCNN_OK) return rc;
+    if (pl.need > kNoAllocTiles)
+        return fail(RDCNN_EINVAL, "%s: the reverse passes of this %dx%d grid use %lld tiles; the "
+                    "static workspace holds %lld (use rdcnn_step_bwd, or fewer, taller segments "
+                    "via rdcnn_set_adjoint_kernel)", who, h->R, h->C, pl.need, kNoAllocTiles);
+    double *ws = nullptr;
+    if ((rc = scratch_address(&ws, who)) != RDCNN_OK) return rc;
+    const size_t n = (size_t)h->R * h->C;
+    float *work = states_dev + (size_t)S * 2 * n;  // slot S: never read as a state
+    Pingpong pp(lam_dev, mu_dev, work, work + n);
+    return run_pairs(h, states_dev, 2, S, pp, pl, ws, dtheta_accum, who);
 }
 
 int rdcnn_set_grad_mask(rdcnn_t h, unsigned mask)
