@@ -21,7 +21,11 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librdcnn.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["rd_api.hip", "rd_forward.hip", "rd_adjoint.hip", "rd_batch.hip", "rd_stats.hip", "rd_models.hip"]
+SOURCES = ["rd_api.hip", "rd_forward.hip", "rd_adjoint.hip", "rd_batch.hip", "rd_stats.hip",
+           "rd_models.hip", "rd_fwd_r0c1.hip", "rd_fwd_r0c2.hip", "rd_fwd_r0c4.hip",
+           "rd_fwd_r1c1.hip", "rd_fwd_r1c2.hip", "rd_fwd_r1c4.hip", "rd_fwd_r23.hip",
+           "rd_adj_plain.hip", "rd_adj_pair.hip", "rd_adj_batch.hip", "rd_batch_r0.hip",
+           "rd_batch_rec.hip"]
 ARCH = "gfx950"
 
 FLAGS = [
@@ -80,8 +84,11 @@ def build(verbose: bool = False, force: bool = True) -> str:
         subprocess.check_call(cmd)
         return obj
 
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
+    # the largest sources first, so they do not start last
+    order = sorted(SOURCES, key=lambda f: -os.path.getsize(os.path.join(CSRC, f)))
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
+        done = dict(zip(order, ex.map(compile_one, order)))
+    objs = [done[f] for f in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -9,66 +9,18 @@
 // grid kernel), each tile carrying its instance's offset, size and parameters,
 // sorted by decreasing work so the longest tiles start first.  A run of T steps
 // is ceil(T/K) such launches, optionally captured once into a HIP graph and
-// replayed.
+// replayed.  The streamed kernel's template is in rd_batch_kernel.h and its
+// instances in rd_batch_r0.hip / rd_batch_rec.hip.
 #include <math.h>
 
 #include <algorithm>
 #include <new>
 #include <vector>
 
-#include "rd_fwd_body.h"
-#include "rd_launch.h"
+#include "rd_batch_kernel.h"
 #include "rdcnn.h"
 
 namespace rd {
-
-struct BatchArgs {
-    const BatchTile *tiles;
-    const BatchInst *insts;
-    int ntiles;
-    const float *in;
-    float *out;
-    int bc, wout, kpad;
-    float *rec;           // packed trajectory, state of level 0 (REC only)
-    unsigned rec_stride;  // bytes between packed states
-};
-
-// REC: 0 plain steps; 1 record every level; 2 record the even levels (passes
-// start at even times); 3 as 2 without level 0 (the input is that state).
-template <int CPL, int K, int REC>
-__global__ __launch_bounds__(64) void batch_step_kernel(BatchArgs B)
-{
-    const int id = blockIdx.x;
-    if (id >= B.ntiles) return;
-    const BatchTile bt = B.tiles[id];
-    const BatchInst in = B.insts[bt.inst];
-    StreamArgs A;
-    A.t.R = in.R;
-    A.t.C = in.C;
-    A.t.bc = B.bc;
-    A.t.wout = B.wout;
-    A.t.kpad = B.kpad;
-    A.t.h = 0;
-    A.t.nsegs = 0;
-    A.t.ntiles = 0;
-    A.t.per_xcd = 0;
-    A.t.vec_ok = (in.C % CPL) == 0;
-    A.in = B.in + in.off;
-    A.out = B.out + in.off;
-    A.g = in.g;
-    A.rec = REC ? B.rec + in.off : nullptr;
-    A.rec_stride = B.rec_stride;
-    Tile<CPL> t;
-    t.setup(A.t, id, bt.x0, bt.y0, bt.y1);
-    if (t.fast) {
-        if (t.y0 >= K && t.y1 + K + kFetchPast <= in.R)
-            stream_body<ModelFHN, CPL, K, REC, true, true>(A, t);
-        else
-            stream_body<ModelFHN, CPL, K, REC, true, false>(A, t);
-    } else {
-        stream_body<ModelFHN, CPL, K, REC, false, false>(A, t);
-    }
-}
 
 // ---------------------------------------------------------------- in-LDS instances
 //
@@ -194,47 +146,12 @@ hipError_t launch_batch_lds(const BatchInst *insts, const int *ids, int count, i
     return hipGetLastError();
 }
 
-namespace {
-
-using BatchFn = void (*)(BatchArgs);
-
-template <int CPL, int REC, int... Ks>
-constexpr BatchFn pick(int k, std::integer_sequence<int, Ks...>)
-{
-    BatchFn f = nullptr;
-    ((f = (k == Ks + 1) ? &batch_step_kernel<CPL, Ks + 1, REC> : f), ...);
-    return f;
-}
-
-}  // namespace
-
 hipError_t launch_batch(const BatchTile *tiles, const BatchInst *insts, int ntiles,
                         const float *in, float *out, int bc, int cpl, int depth, hipStream_t s,
                         float *rec, unsigned rec_stride, bool rec_even, bool skip_level0)
 {
-    BatchFn f = nullptr;
-    if (rec && rec_even && skip_level0) {  // recording passes: cpl 1 or 2, depth <= 8
-        if (cpl == 2)
-            f = pick<2, 3>(depth, std::make_integer_sequence<int, 8>{});
-        else if (cpl == 1)
-            f = pick<1, 3>(depth, std::make_integer_sequence<int, 8>{});
-    } else if (rec && rec_even) {
-        if (cpl == 2)
-            f = pick<2, 2>(depth, std::make_integer_sequence<int, 8>{});
-        else if (cpl == 1)
-            f = pick<1, 2>(depth, std::make_integer_sequence<int, 8>{});
-    } else if (rec) {
-        if (cpl == 2)
-            f = pick<2, 1>(depth, std::make_integer_sequence<int, 8>{});
-        else if (cpl == 1)
-            f = pick<1, 1>(depth, std::make_integer_sequence<int, 8>{});
-    } else if (cpl == 4) {
-        f = pick<4, 0>(depth, std::make_integer_sequence<int, kMaxDepthCpl4>{});
-    } else if (cpl == 2) {
-        f = pick<2, 0>(depth, std::make_integer_sequence<int, kMaxDepthCpl2>{});
-    } else if (cpl == 1) {
-        f = pick<1, 0>(depth, std::make_integer_sequence<int, kMaxDepthCpl1>{});
-    }
+    BatchFn f = !rec ? batch_fn_r0(cpl, depth)
+                     : batch_fn_rec(rec_even ? (skip_level0 ? 3 : 2) : 1, cpl, depth);
     if (!f || ntiles < 1) return hipErrorInvalidValue;
     BatchArgs a;
     a.tiles = tiles;

@@ -17,9 +17,9 @@
 //                       side and the segment K halo rows above and below (the
 //                       valid region shrinks by one cell per level), read from
 //                       the boundary-extended grid (map_index), so the boundary
-//                       rule costs nothing inside the loop.
-#include "rd_fwd_body.h"
-#include "rd_launch.h"
+//                       rule costs nothing inside the loop.  Its template
+//                       instances are compiled in rd_fwd_r*.hip.
+#include "rd_fwd_kernel.h"
 
 namespace rd {
 
@@ -111,21 +111,6 @@ hipError_t launch_naive(const float *in, float *out, int R, int C, int bc, const
 
 // ---------------------------------------------------------------- streamed
 
-template <int CPL, int K, int REC>
-__global__ __launch_bounds__(64) void stream_step_kernel(StreamArgs A)
-{
-    Tile<CPL> t;
-    if (!t.init(A.t)) return;
-    if (t.fast) {
-        if (t.y0 >= K && t.y1 + K + kFetchPast <= A.t.R)
-            stream_body<ModelFHN, CPL, K, REC, true, true>(A, t);
-        else
-            stream_body<ModelFHN, CPL, K, REC, true, false>(A, t);
-    } else {
-        stream_body<ModelFHN, CPL, K, REC, false, false>(A, t);
-    }
-}
-
 bool stream_geometry(int R, int C, int cpl, int depth, int seg_rows, StreamGeom *g)
 {
     if (cpl != 1 && cpl != 2 && cpl != 4) return false;
@@ -156,27 +141,18 @@ bool stream_geometry(int R, int C, int cpl, int depth, int seg_rows, StreamGeom 
 
 namespace {
 
-using StreamFn = void (*)(StreamArgs);
-
-template <int CPL, int REC, int... Ks>
-constexpr StreamFn pick(int k, std::integer_sequence<int, Ks...>)
+// The instance for a pass: recording mode rec (rd_fwd_body.h), cpl columns per
+// lane, depth steps; null if there is none.
+StreamFn pick_stream(int rec, int cpl, int depth)
 {
-    StreamFn f = nullptr;
-    ((f = (k == Ks + 1) ? &stream_step_kernel<CPL, Ks + 1, REC> : f), ...);
-    return f;
-}
-
-template <int REC>
-StreamFn pick_stream(int cpl, int depth)
-{
-    if (REC >= 2) {  // even-state recording: one or two columns per lane, depth <= 8
-        if (cpl == 2) return pick<2, REC>(depth, std::make_integer_sequence<int, 8>{});
-        if (cpl == 1) return pick<1, REC>(depth, std::make_integer_sequence<int, 8>{});
+    if (rec >= 2) {  // even-state recording: one or two columns per lane, depth <= 8
+        if (cpl == 1) return rec == 2 ? stream_fn_r2c1(depth) : stream_fn_r3c1(depth);
+        if (cpl == 2) return rec == 2 ? stream_fn_r2c2(depth) : stream_fn_r3c2(depth);
         return nullptr;
     }
-    if (cpl == 4) return pick<4, REC>(depth, std::make_integer_sequence<int, kMaxDepthCpl4>{});
-    if (cpl == 2) return pick<2, REC>(depth, std::make_integer_sequence<int, kMaxDepthCpl2>{});
-    if (cpl == 1) return pick<1, REC>(depth, std::make_integer_sequence<int, kMaxDepthCpl1>{});
+    if (cpl == 4) return rec ? stream_fn_r1c4(depth) : stream_fn_r0c4(depth);
+    if (cpl == 2) return rec ? stream_fn_r1c2(depth) : stream_fn_r0c2(depth);
+    if (cpl == 1) return rec ? stream_fn_r1c1(depth) : stream_fn_r0c1(depth);
     return nullptr;
 }
 
@@ -203,10 +179,7 @@ hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, cons
                          bool rec_even, bool skip_level0, int rec_every)
 {
     if (rec_every < 1) return hipErrorInvalidValue;
-    StreamFn f = !rec ? pick_stream<0>(geom.cpl, geom.depth)
-                 : !rec_even ? pick_stream<1>(geom.cpl, geom.depth)
-                 : skip_level0 ? pick_stream<3>(geom.cpl, geom.depth)
-                               : pick_stream<2>(geom.cpl, geom.depth);
+    StreamFn f = pick_stream(!rec ? 0 : !rec_even ? 1 : skip_level0 ? 3 : 2, geom.cpl, geom.depth);
     if (!f) return hipErrorInvalidValue;
     StreamArgs a;
     a.t = tile_args(R, C, bc, geom);
