@@ -325,8 +325,16 @@ def bench_plain(stream):
     state = sim.read_host()  # s_T, compared with the oracle in the CPU leg
     t = min(_timed(lambda: sim.step(T), stream) for _ in range(3))
     sim.close()
+    # the same run replayed from a captured HIP graph (rdcnn_use_graph)
+    sim = Simulation(x, W.PLAIN_GENE, "zeroflux").use_graph(True)
+    sim.step(T)  # captures the graph from buffer 0 (an odd pass count flips the buffer)
+    same = bool(np.array_equal(sim.read_host()[0], state[0]))
+    sim.step(T)  # ... and from buffer 1
+    tg = min(_timed(lambda: sim.step(T), stream) for _ in range(4))
+    sim.close()
     return {"workload": "256x256 zero-flux, T=1000, x~U[-1,1]", "gcells": N * N * T / t / 1e9,
-            "ms": t * 1e3}, state
+            "ms": t * 1e3, "graph_gcells": N * N * T / tg / 1e9, "graph_ms": tg * 1e3,
+            "graph_first_T_bitwise_equal": same}, state
 
 
 def bench_edge_fit(stream, n_img=64, iters=4):

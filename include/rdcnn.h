@@ -136,6 +136,19 @@ int rdcnn_model_create(rdcnn_t *out, int model, int rows, int cols, int bc, cons
 int rdcnn_step(rdcnn_t h, long long T);
 
 /*
+ * rdcnn_use_graph -- on != 0: rdcnn_step captures the launch sequence of its T
+ * steps into a HIP graph the first time and replays that graph afterwards
+ * (one cached graph per starting buffer, rebuilt when T changes; dropped by
+ * rdcnn_set_params and rdcnn_set_kernel, whose values the captured launches
+ * carry).  This removes the host's per-launch cost for short runs of small
+ * grids, where a pass takes a few microseconds.  Results are bit-identical to
+ * rdcnn_step without graphs.  The handle's stream must not be the NULL stream.
+ * on == 0 drops the graphs.  Errors: RDCNN_EINVAL; capture or instantiation
+ * failures later surface from rdcnn_step as RDCNN_EHIP.
+ */
+int rdcnn_use_graph(rdcnn_t h, int on);
+
+/*
  * rdcnn_read -- copy the current state (the paper's snapshot of A and B,
  * Sec. II.B main loop) into u_dst and v_dst, rows*cols floats each.
  * dst_is_host != 0: host destinations; the call waits for the stream.
@@ -302,7 +315,37 @@ int rdcnn_step_bwd(rdcnn_t h, float *states_dev, long long S, float *lam_dev, fl
                    double *dtheta_accum);
 
 /*
- * rdcnn_step_bwd_noalloc -- rdcnn_step_bwd for callers that cannot allocate
+ * rdcnn_step_bwd_ckpt -- the whole backward half of checkpoint-and-recompute
+ * for T steps whose forward kept a checkpoint every S steps
+ * (rdcnn_step_checkpoints): for the segments from last to first, restore the
+ * checkpoint, re-run the segment recording the states of its even times
+ * (rdcnn_step_record_sparse's layout) and run the reverse passes of
+ * rdcnn_step_bwd through it.  The recompute of segment k runs on a second
+ * stream (made by the library on first use, default priority, destroyed with
+ * the handle) while the reverse passes of segment k+1 run on the handle's
+ * stream; the two alternate between the two halves of work_dev.  The partial
+ * sums of all segments go to one buffer, folded once at the end.
+ *   ckpt_dev     device, ceil(T/S) states of 2*rows*cols floats: checkpoint j =
+ *                s_{t0+jS} (read only)
+ *   T, S         steps (T >= 0; 0 does nothing) and checkpoint spacing (S >= 1)
+ *   work_dev     device, 2*(min(S,T)+1) states of 2*rows*cols floats (scratch;
+ *                overlaps neither ckpt_dev, lam_dev nor mu_dev)
+ *   lam_dev      rows*cols floats: on entry dJ/du at t0+T, on return dJ/du at t0
+ *   mu_dev       the same for v (distinct from lam_dev)
+ *   dtheta_accum 8 device doubles: dJ/dp is ADDED (order dt, a, b, eps, c, k3,
+ *                Du, Dv) for the parameters of the gradient mask; NaN for the others
+ * Results: (lam, mu) bit-identical to rdcnn_step_bwd run segment by segment
+ * on the same recomputed states; dtheta equal up to the order of its final
+ * double-precision sum.  Deterministic.  Asynchronous with respect to the host;
+ * all work is ordered after the handle's earlier work and before its later
+ * work.  Errors: RDCNN_EINVAL (NULL or overlapping buffers, T < 0, S < 1, not a
+ * FitzHugh-Nagumo grid, grid too large to record), RDCNN_ENOMEM, RDCNN_EHIP.
+ */
+int rdcnn_step_bwd_ckpt(rdcnn_t h, const float *ckpt_dev, long long T, long long S,
+                        float *work_dev, float *lam_dev, float *mu_dev, double *dtheta_accum);
+
+/*
+ * rdcnn_step_bwd_noalloc --rdcnn_step_bwd for callers that cannot allocate
  * device memory: code being captured into a HIP graph, tight serving loops,
  * harnesses that forbid hipMalloc.  Same arguments, kernels, launch order and
  * results (bit for bit) as rdcnn_step_bwd; the per-tile partial sums live in

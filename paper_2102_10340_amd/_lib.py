@@ -47,6 +47,7 @@ _SIGS = {
     "rdcnn_create": [_PP, _I, _I, _I, _PAR, _P, _F, _P, _P, _P],
     "rdcnn_model_create": [_PP, _I, _I, _I, _I, _P, _I, _P, _P, _P, _P, _P],
     "rdcnn_step": [_P, _LL],
+    "rdcnn_use_graph": [_P, _I],
     "rdcnn_read": [_P, _P, _P, _I],
     "rdcnn_write_state": [_P, _P, _P],
     "rdcnn_set_params": [_P, _PAR],
@@ -62,6 +63,7 @@ _SIGS = {
     "rdcnn_step_checkpoints": [_P, _LL, _LL, _P],
     "rdcnn_step_bwd": [_P, _P, _LL, _P, _P, _P],
     "rdcnn_step_bwd_noalloc": [_P, _P, _LL, _P, _P, _P],
+    "rdcnn_step_bwd_ckpt": [_P, _P, _LL, _LL, _P, _P, _P, _P],
     "rdcnn_set_check_finite": [_P, _I],
     "rdcnn_set_adjoint_kernel": [_P, _I, _I, _I],
     "rdcnn_init_backward": [_P, _LL, _F, _P, _P],

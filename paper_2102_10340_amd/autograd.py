@@ -8,11 +8,12 @@ equal those of a fully recorded trajectory.  The schedule is chosen by S:
 * S = 0 (default) or S > 0, checkpoint-and-recompute (the differentiation
   workload's schedule): the forward keeps one checkpoint every S steps
   (rdcnn_step_checkpoints; each is written by the pass that ends there); the
-  backward walks the segments from last to first, restores a checkpoint,
-  re-runs the segment recording its even states (rdcnn_step_record_sparse)
-  and runs rdcnn_step_bwd through them.  The recompute of segment k needs only
-  checkpoint k, so it runs on a second stream while the reverse pass of
-  segment k+1 runs on the caller's stream (two segment buffers in turn).
+  backward (rdcnn_step_bwd_ckpt) walks the segments from last to first,
+  re-runs each from its checkpoint recording its even states and runs the
+  reverse passes of rdcnn_step_bwd through them.  The recompute of segment k
+  needs only checkpoint k, so the library runs it on a second stream while
+  the reverse pass of segment k+1 runs on the caller's stream (two segment
+  buffers in turn).
   S = 0 picks S = ceil(sqrt(T)) rounded up to the forward's pass depth of 8,
   so checkpoints fall on pass boundaries: O(sqrt(T)) states of memory.
 * S = -1, whole trajectory: the forward records the even states of all T
@@ -69,18 +70,6 @@ def _gene(theta: torch.Tensor):
     return dict(zip(PARAM_FIELDS, vals))
 
 
-_SIDE_STREAMS = {}
-
-
-def _side_stream(device) -> torch.cuda.Stream:
-    """One extra stream per device (default priority) for the recompute."""
-    key = torch.device(device).index or 0
-    s = _SIDE_STREAMS.get(key)
-    if s is None:
-        s = _SIDE_STREAMS[key] = torch.cuda.Stream(device)
-    return s
-
-
 def _forward(sim: Simulation, T: int, S: int, dev, record: bool = True):
     """Run T steps; returns (u_T, v_T, saved states, number of segments)."""
     R, C = sim.rows, sim.cols
@@ -123,34 +112,11 @@ def _backward(sim: Simulation, ckpt, nseg: int, T: int, S: int, gu, gv, dev, ker
             sim.step_record_sparse(L, seg)
             sim.step_bwd(seg, L, lam, mu, dtheta)
         return lam, mu, dtheta
-    # Recompute segment k on the side stream (its own handle) while the
-    # reverse pass of segment k+1 runs on the caller's stream; two segment
-    # buffers in turn, each re-recorded only after the reverse pass that
-    # read it has finished.
-    main = torch.cuda.current_stream(dev)
-    side = _side_stream(dev)
-    segs = [torch.empty((Smax + 1, 2, R, C), dtype=torch.float32, device=dev) for _ in range(2)]
-    side.wait_stream(main)
-    with torch.cuda.stream(side):
-        rsim = Simulation(ckpt[0, 0], sim.gene, sim.bc, 1.0)
-        rsim.set_kernel(*sim.kernel_setting())
-    done = [None, None]
-    for idx, k in enumerate(range(nseg - 1, -1, -1)):
-        L = min(S, T - k * S)
-        b = idx % 2
-        with torch.cuda.stream(side):
-            if done[b] is not None:
-                side.wait_event(done[b])
-            rsim.write_state_packed(ckpt[k])
-            rsim.step_record_sparse(L, segs[b])
-            ready = torch.cuda.Event()
-            ready.record(side)
-        main.wait_event(ready)
-        sim.step_bwd(segs[b], L, lam, mu, dtheta)
-        done[b] = torch.cuda.Event()
-        done[b].record(main)
-    main.wait_stream(side)
-    rsim.close()
+    # The library runs the whole schedule: segment k recomputed on its second
+    # stream while the reverse pass of segment k+1 runs on this one, two
+    # segment buffers in turn, the partial sums folded once at the end.
+    work = torch.empty((2 * (Smax + 1), 2, R, C), dtype=torch.float32, device=dev)
+    sim.step_bwd_ckpt(ckpt, T, S, work, lam, mu, dtheta)
     return lam, mu, dtheta
 
 

@@ -33,6 +33,14 @@ struct rdcnn_sim {
     float mparams[rd::kModelParams];       // parameters of the other models
     int check_finite;                      // rdcnn_read checks the state for NaN / Inf
     int *finite_flag;                      // device counter of that check (made on first use)
+    hipStream_t side;                      // rdcnn_step_bwd_ckpt's recompute stream (made on first use)
+    hipEvent_t ev[5];                      // its events: ready[2], done[2], start
+    int use_graph;                         // rdcnn_step replays captured launch sequences
+    struct StepGraph {
+        hipGraphExec_t exec;  // null: empty entry
+        long long T;          // steps it runs
+        int cur0, cur1;       // buffer holding the state before / after
+    } graph[2];               // one per starting buffer
 };
 
 namespace {
@@ -322,6 +330,55 @@ int run_model_steps(rdcnn_sim *h, long long n)
     return RDCNN_OK;
 }
 
+// Even-time recording of n steps from the state at `in` on stream s: passes
+// of `depth` (even) steps; every pass but the last writes its output straight
+// into the trajectory slot of the (even) time it ends at (s_{2i} at rec + 2i *
+// every / 2 states, i.e. rec + i * every states), and the next pass reads its
+// input from there and records from level 2 on, so each recorded state is
+// written once.  No pass reads a slot it writes.  The last pass writes
+// last_out.  The first pass records its input as s_0.
+int record_even_chain(const rdcnn_sim *h, const float *in, long long n, float *rec, int every,
+                      float *last_out, int cpl, int depth, int seg, hipStream_t s, const char *who)
+{
+    const size_t state = 2 * (size_t)h->R * h->C;
+    long long q = 0;
+    while (n > 0) {
+        const int k = (int)(n < depth ? n : depth);
+        float *out = n == k ? last_out : rec + (size_t)((q + k) / 2) * every * state;
+        rd::StreamGeom geom;
+        if (!rd::stream_geometry(h->R, h->C, cpl, k, seg, &geom))
+            return fail(RDCNN_EINVAL, "%s: cannot tile %dx%d with cpl=%d depth=%d", who, h->R, h->C,
+                        cpl, k);
+        hipError_t e = rd::launch_stream(in, out, h->R, h->C, h->bc, h->g, geom, s, rec, q / 2, true,
+                                         q > 0, every);
+        if (e != hipSuccess) return hip_fail(e, who);
+        in = out;
+        n -= k;
+        q += k;
+    }
+    return RDCNN_OK;
+}
+
+// Pass shape of an even-time recording run: the handle's forced streamed
+// settings, else the automatic ones, made even (<= 8) with one or two columns
+// per lane and cut so a pass's recorded states (`every` slots apart) fit one
+// buffer resource.  Returns false if the grid is too large to record.
+bool even_record_shape(const rdcnn_sim *h, int every, int *cpl, int *depth, int *seg)
+{
+    *cpl = h->cpl;
+    *depth = h->depth;
+    *seg = h->seg_rows;
+    if (h->kind != 2) auto_config(h, cpl, depth, seg, true, true);
+    const long long cap = ((1LL << 32) - 1) / (8LL * h->R * h->C);
+    if (cap < 1) return false;
+    if (*cpl > 2) *cpl = 2;
+    if (*depth > 8) *depth = 8;
+    const long long dmax = 2 * ((cap - 1) / every + 1);
+    if (*depth > dmax) *depth = (int)dmax;
+    if (*depth > 1) *depth &= ~1;
+    return *depth >= 2;
+}
+
 // Run n steps from buf[cur]; flips cur once per pass.  If rec is not null the
 // state each step starts from is also written to rec[0..n-1] (2*R*C floats
 // each); with rec_even only the states of even times, s_{2i} to rec[i * every]
@@ -359,27 +416,9 @@ int run_steps(rdcnn_sim *h, long long n, float *rec, bool rec_even = false, int 
         }
     }
     if (rec && rec_even && kind == 2 && depth >= 2 && n > 0) {
-        // Every pass but the last writes its output straight into the
-        // trajectory slot of the (even) time it ends at; the next pass reads
-        // its input from there and records from level 2 on, so each recorded
-        // state is written once.  No pass reads a slot it writes.  The last
-        // pass writes the handle's other buffer.
-        const size_t state = 2 * (size_t)h->R * h->C;
-        const float *in = h->buf[h->cur];
-        while (n > 0) {
-            const int k = (int)(n < depth ? n : depth);
-            float *out = n == k ? h->buf[1 - h->cur] : rec + (size_t)((q + k) / 2) * every * state;
-            rd::StreamGeom geom;
-            if (!rd::stream_geometry(h->R, h->C, cpl, k, seg, &geom))
-                return fail(RDCNN_EINVAL, "rdcnn_step: cannot tile %dx%d with cpl=%d depth=%d",
-                            h->R, h->C, cpl, k);
-            hipError_t e = rd::launch_stream(in, out, h->R, h->C, h->bc, h->g, geom, h->stream,
-                                             rec, q / 2, true, q > 0, every);
-            if (e != hipSuccess) return hip_fail(e, "rdcnn_step: kernel launch");
-            in = out;
-            n -= k;
-            q += k;
-        }
+        const int rc = record_even_chain(h, h->buf[h->cur], n, rec, every, h->buf[1 - h->cur], cpl,
+                                         depth, seg, h->stream, "rdcnn_step");
+        if (rc != RDCNN_OK) return rc;
         h->cur = 1 - h->cur;
         return RDCNN_OK;
     }
@@ -414,6 +453,53 @@ int run_steps(rdcnn_sim *h, long long n, float *rec, bool rec_even = false, int 
         n -= done;
         q += done;
     }
+    return RDCNN_OK;
+}
+
+// Captured step sequences bake in the parameters and pass settings: drop them
+// when either changes.
+void drop_graphs(rdcnn_sim *h)
+{
+    for (auto &gr : h->graph) {
+        if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+        gr.exec = nullptr;
+    }
+}
+
+// rdcnn_step with graphs on: the launch sequence of T steps from buf[cur] is
+// captured once (run_steps only launches kernels) and replayed after that.
+int step_graph(rdcnn_sim *h, long long T)
+{
+    auto &gr = h->graph[h->cur];
+    if (!(gr.exec && gr.T == T && gr.cur0 == h->cur)) {
+        if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+        gr.exec = nullptr;
+        const int cur0 = h->cur;
+        hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) return hip_fail(e, "rdcnn_step: begin capture");
+        const int rc = run_steps(h, T, nullptr);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(h->stream, &g);
+        const int cur1 = h->cur;
+        h->cur = cur0;
+        if (rc != RDCNN_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "rdcnn_step: end capture");
+        e = hipGraphInstantiate(&gr.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            gr.exec = nullptr;
+            return hip_fail(e, "rdcnn_step: graph instantiate");
+        }
+        gr.T = T;
+        gr.cur0 = cur0;
+        gr.cur1 = cur1;
+    }
+    hipError_t e = hipGraphLaunch(gr.exec, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "rdcnn_step: graph launch");
+    h->cur = gr.cur1;
     return RDCNN_OK;
 }
 
@@ -492,6 +578,10 @@ rdcnn_sim *new_sim(int rows, int cols, int bc, float *buf0, float *buf1, void *s
     for (float &x : h->mparams) x = 0.0f;
     h->check_finite = 0;
     h->finite_flag = nullptr;
+    h->side = nullptr;
+    for (hipEvent_t &e : h->ev) e = nullptr;
+    h->use_graph = 0;
+    for (auto &gr : h->graph) gr.exec = nullptr;
     return h;
 }
 
@@ -574,7 +664,18 @@ int rdcnn_step(rdcnn_t h, long long T)
 {
     if (!h) return fail(RDCNN_EINVAL, "rdcnn_step: NULL handle");
     if (T < 0) return fail(RDCNN_EINVAL, "rdcnn_step: T = %lld < 0", T);
+    if (h->use_graph && T > 0) return step_graph(h, T);
     return run_steps(h, T, nullptr);
+}
+
+int rdcnn_use_graph(rdcnn_t h, int on)
+{
+    if (!h) return fail(RDCNN_EINVAL, "rdcnn_use_graph: NULL handle");
+    if (on && !h->stream)
+        return fail(RDCNN_EINVAL, "rdcnn_use_graph: graph capture needs a non-NULL stream");
+    h->use_graph = on ? 1 : 0;
+    if (!on) drop_graphs(h);
+    return RDCNN_OK;
 }
 
 int rdcnn_step_record(rdcnn_t h, long long T, float *states_dev)
@@ -730,10 +831,14 @@ int plan_pairs(const rdcnn_sim *h, long long S, int every, const char *who, Pair
 // (state s_{t0+2i} at states + i * every states), ping-ponging (lam, mu)
 // between pp's two pairs of planes; the per-tile sums go to `partial` (need
 // tiles, zeroed here) and are folded into dtheta.
+// zero / fold: clear the partials first / fold them into dtheta at the end
+// (a chain of segments clears once and folds once).
 int run_pairs(rdcnn_sim *h, const float *states, int every, long long S, Pingpong &pp,
-              const PairPlan &pl, double *partial, double *dtheta, const char *who)
+              const PairPlan &pl, double *partial, double *dtheta, const char *who,
+              bool zero = true, bool fold = true)
 {
-    hipError_t e = rd::launch_zero(partial, rd::kAdjSums * pl.need, h->stream);
+    hipError_t e = hipSuccess;
+    if (zero) e = rd::launch_zero(partial, rd::kAdjSums * pl.need, h->stream);
     if (e != hipSuccess) return hip_fail(e, who);
     const bool lam_sums = (h->grad_mask & kLamSumGrads) != 0;
     const long long even = S & ~1LL;
@@ -759,7 +864,7 @@ int run_pairs(rdcnn_sim *h, const float *states, int every, long long S, Pingpon
     }
     e = pp.copy_back((size_t)h->R * h->C, h->stream);
     if (e != hipSuccess) return hip_fail(e, who);
-    e = rd::launch_adjoint_finish(partial, (int)pl.need, h->g, h->grad_mask, dtheta, h->stream);
+    if (fold) e = rd::launch_adjoint_finish(partial, (int)pl.need, h->g, h->grad_mask, dtheta, h->stream);
     if (e != hipSuccess) return hip_fail(e, who);
     return RDCNN_OK;
 }
@@ -924,6 +1029,95 @@ int rdcnn_step_bwd_noalloc(rdcnn_t h, float *states_dev, long long S, float *lam
     return run_pairs(h, states_dev, 2, S, pp, pl, ws, dtheta_accum, who);
 }
 
+int rdcnn_step_bwd_ckpt(rdcnn_t h, const float *ckpt_dev, long long T, long long S,
+                        float *work_dev, float *lam_dev, float *mu_dev, double *dtheta_accum)
+{
+    const char *who = "rdcnn_step_bwd_ckpt";
+    if (!h) return fail(RDCNN_EINVAL, "%s: NULL handle", who);
+    if (h->model != rd::MODEL_FHN) return fail(RDCNN_EINVAL, "%s: FitzHugh-Nagumo grids only", who);
+    if (T < 0 || S < 1) return fail(RDCNN_EINVAL, "%s: T = %lld, S = %lld", who, T, S);
+    if (T == 0) return RDCNN_OK;
+    if (!ckpt_dev || !work_dev || !lam_dev || !mu_dev || !dtheta_accum)
+        return fail(RDCNN_EINVAL, "%s: NULL argument", who);
+    const size_t n = (size_t)h->R * h->C, state = 2 * n;
+    const long long nseg = (T + S - 1) / S;
+    const long long Smax = S < T ? S : T;
+    {
+        auto overlap = [](const void *x, size_t nx, const void *y, size_t ny) {
+            const char *a = (const char *)x, *b = (const char *)y;
+            return a < b + ny && b < a + nx;
+        };
+        const size_t pb = sizeof(float) * n;
+        const size_t wb = sizeof(float) * state * 2 * (size_t)(Smax + 1);
+        const size_t cb = sizeof(float) * state * (size_t)nseg;
+        if (overlap(lam_dev, pb, mu_dev, pb)) return fail(RDCNN_EINVAL, "%s: lam and mu overlap", who);
+        if (overlap(work_dev, wb, lam_dev, pb) || overlap(work_dev, wb, mu_dev, pb) ||
+            overlap(work_dev, wb, ckpt_dev, cb))
+            return fail(RDCNN_EINVAL, "%s: the workspace overlaps lam, mu or the checkpoints", who);
+    }
+    int cpl, depth, seg;
+    if (!even_record_shape(h, 2, &cpl, &depth, &seg))
+        return fail(RDCNN_EINVAL, "%s: grid too large to record", who);
+    // One partial buffer for every segment: cleared once, folded once.
+    const long long Llast = T - (nseg - 1) * S;
+    PairPlan pl, plast;
+    int rc = plan_pairs(h, Smax, 2, who, &pl);
+    if (rc == RDCNN_OK) rc = plan_pairs(h, Llast, 2, who, &plast);
+    if (rc != RDCNN_OK) return rc;
+    const long long need = pl.need > plast.need ? pl.need : plast.need;
+    if ((rc = ensure_partial(h, need, who)) != RDCNN_OK) return rc;
+    hipError_t e = hipSuccess;
+    if (!h->side) {
+        e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            h->side = nullptr;
+            return hip_fail(e, who);
+        }
+        for (hipEvent_t &ev : h->ev) {
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                ev = nullptr;
+                return hip_fail(e, who);
+            }
+        }
+    }
+    hipEvent_t *ready = h->ev, *done = h->ev + 2, start = h->ev[4];
+    e = rd::launch_zero(h->partial, rd::kAdjSums * need, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(start, h->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(h->side, start, 0);  // the caller's earlier work
+    if (e != hipSuccess) return hip_fail(e, who);
+    float *segbuf[2] = {work_dev, work_dev + (size_t)(Smax + 1) * state};
+    for (long long idx = 0; idx < nseg; ++idx) {
+        const long long k = nseg - 1 - idx;
+        const long long L = k == nseg - 1 ? Llast : S;
+        const int b = (int)(idx & 1);
+        float *traj = segbuf[b];
+        // Recompute segment k on the side stream once the reverse pass that
+        // read this buffer two segments ago is done; its final state goes to
+        // slot L, the reverse passes' workspace (never read as a state).
+        if (idx >= 2 && (e = hipStreamWaitEvent(h->side, done[b], 0)) != hipSuccess)
+            return hip_fail(e, who);
+        rc = record_even_chain(h, ckpt_dev + (size_t)k * state, L, traj, 2, traj + (size_t)L * state,
+                               cpl, depth, seg, h->side, who);
+        if (rc != RDCNN_OK) return rc;
+        if ((e = hipEventRecord(ready[b], h->side)) != hipSuccess ||
+            (e = hipStreamWaitEvent(h->stream, ready[b], 0)) != hipSuccess)
+            return hip_fail(e, who);
+        // Reverse passes of segment k on the handle's stream, overlapping the
+        // recompute of segment k-1.
+        PairPlan plk;
+        if ((rc = plan_pairs(h, L, 2, who, &plk)) != RDCNN_OK) return rc;
+        float *ws = traj + (size_t)L * state;
+        Pingpong pp(lam_dev, mu_dev, ws, ws + n);
+        rc = run_pairs(h, traj, 2, L, pp, plk, h->partial, dtheta_accum, who, false, false);
+        if (rc != RDCNN_OK) return rc;
+        if ((e = hipEventRecord(done[b], h->stream)) != hipSuccess) return hip_fail(e, who);
+    }
+    e = rd::launch_adjoint_finish(h->partial, (int)need, h->g, h->grad_mask, dtheta_accum, h->stream);
+    if (e != hipSuccess) return hip_fail(e, who);
+    return RDCNN_OK;
+}
+
 int rdcnn_set_grad_mask(rdcnn_t h, unsigned mask)
 {
     if (!h) return fail(RDCNN_EINVAL, "rdcnn_set_grad_mask: NULL handle");
@@ -983,6 +1177,7 @@ int rdcnn_set_params(rdcnn_t h, const rdcnn_params_t *p)
     if (h->model != rd::MODEL_FHN)
         return fail(RDCNN_EINVAL, "rdcnn_set_params: FitzHugh-Nagumo grids only");
     h->g = to_gene(p);
+    drop_graphs(h);
     return RDCNN_OK;
 }
 
@@ -996,6 +1191,7 @@ int rdcnn_current(rdcnn_t h, float **state_dev)
 int rdcnn_set_kernel(rdcnn_t h, int kind, int depth, int cols_per_lane, int seg_rows)
 {
     if (!h) return fail(RDCNN_EINVAL, "rdcnn_set_kernel: NULL handle");
+    drop_graphs(h);
     if (kind == 0 || kind == 1) {
         h->kind = kind;
         return RDCNN_OK;
@@ -1052,6 +1248,13 @@ int rdcnn_destroy(rdcnn_t h)
     if (!h) return RDCNN_OK;
     pool_put(h->partial_device, h->partial_cap, h->partial, h->stream);
     if (h->finite_flag) (void)hipFree(h->finite_flag);
+    if (h->side) {
+        (void)hipStreamSynchronize(h->side);
+        (void)hipStreamDestroy(h->side);
+    }
+    for (hipEvent_t e : h->ev)
+        if (e) (void)hipEventDestroy(e);
+    drop_graphs(h);
     delete h;
     return RDCNN_OK;
 }

@@ -20,7 +20,7 @@ namespace rd {
 
 // Level-0 rows are fetched this many iterations before their first use
 // (at most kFetchPast: the last fetches name rows past the walk).
-constexpr int kFwdFetch = 2;
+constexpr int kFwdFetch = 3;
 static_assert(kFwdFetch >= 1 && kFwdFetch <= kFetchPast, "level-0 fetch distance");
 
 template <class M>

@@ -94,6 +94,12 @@ class Simulation:
         check(lib.rdcnn_step(self._h, int(T)))
         return self
 
+    def use_graph(self, on: bool = True) -> "Simulation":
+        """rdcnn_use_graph: step() replays a captured HIP graph of its launches
+        (per T and starting buffer).  Needs a non-default current stream."""
+        check(lib.rdcnn_use_graph(self._h, 1 if on else 0))
+        return self
+
     def step_record(self, T: int, states: torch.Tensor) -> "Simulation":
         """Advance by T steps and write the state each step starts from into
         states[0..T-1] (a float32 CUDA tensor of shape [>= T, 2, R, C])."""
@@ -144,6 +150,26 @@ class Simulation:
             raise ValueError("dtheta must be a CUDA float64 tensor of 8 elements")
         check(lib.rdcnn_step_bwd(self._h, states.data_ptr() if S > 0 else None, int(S),
                                  lam.data_ptr(), mu.data_ptr(), dtheta.data_ptr()))
+
+    def step_bwd_ckpt(self, ckpt: torch.Tensor, T: int, S: int, work: torch.Tensor,
+                      lam: torch.Tensor, mu: torch.Tensor, dtheta: torch.Tensor) -> None:
+        """rdcnn_step_bwd_ckpt: the backward of checkpoint-and-recompute through
+        T steps whose checkpoints (one every S steps) sit in ckpt; each segment
+        is recomputed on the library's second stream while the reverse pass of
+        the next runs.  work: [>= 2 (min(S, T) + 1), 2, R, C] scratch.  lam, mu
+        ([R, C]) go from dJ/d(u, v) after the T steps to before them; dJ/dp
+        (float64 [8]) is added to dtheta."""
+        if T > 0:
+            self._check_states(ckpt, -(-int(T) // int(S)))
+            self._check_states(work, 2 * (min(int(S), int(T)) + 1))
+        for t in (lam, mu):
+            if t.shape != (self.rows, self.cols) or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError("lam and mu must be contiguous float32 [R, C]")
+        if dtheta.dtype != torch.float64 or dtheta.numel() != 8 or not dtheta.is_cuda:
+            raise ValueError("dtheta must be a CUDA float64 tensor of 8 elements")
+        check(lib.rdcnn_step_bwd_ckpt(self._h, ckpt.data_ptr() if T > 0 else None, int(T), int(S),
+                                      work.data_ptr() if T > 0 else None, lam.data_ptr(),
+                                      mu.data_ptr(), dtheta.data_ptr()))
 
     def set_check_finite(self, on: bool = True) -> None:
         """Reads check the state for NaN / Inf and raise (RDCNN_ENONFINITE)."""

@@ -1,7 +1,8 @@
 """GPU tests of the checkpoint-and-recompute entry points: rdcnn_step_checkpoints
 (forward with a checkpoint every S steps), rdcnn_step_record_sparse (even-time
-states in their own slots) and rdcnn_step_bwd (the reverse pass through one
-segment), called through the C ABI, against the CPU oracle's float64 reverse
+states in their own slots), rdcnn_step_bwd (the reverse pass through one
+segment) and rdcnn_step_bwd_ckpt (the whole recompute-and-reverse schedule),
+called through the C ABI, against the CPU oracle's float64 reverse
 pass on the same float32 trajectory (bars as in test_gpu_adjoint: 1e-4
 relative max-norm on dJ/ds, 1e-3 on dJ/dp), plus the finite check on reads,
 the batch's packed read and its shared-parameter gradient sum."""
@@ -126,6 +127,78 @@ def test_step_checkpoints_bitwise(bc, T, S):
         u, v = oracle.run(u, v, g, bc, min(S, T - j * S), "f32")
     got = sim.read_host()
     assert np.array_equal(got[0], u) and np.array_equal(got[1], v)
+    sim.close()
+
+
+@pytest.mark.parametrize("T,S", [(1, 1), (23, 50), (40, 8), (45, 7), (45, 45), (100, 16), (61, 12)])
+@pytest.mark.parametrize("bc", BCS)
+def test_step_bwd_ckpt_through_cabi(bc, T, S):
+    """rdcnn_step_bwd_ckpt (the library's checkpoint-and-recompute backward,
+    recompute on a second stream) called with raw device pointers: (lam, mu)
+    bit for bit equal to rdcnn_step_bwd run segment by segment on a serially
+    recomputed trajectory, dJ/dp equal up to the order of the final double
+    sum, and both against the oracle's float64 reverse pass (1e-4 / 1e-3)."""
+    from paper_2102_10340_amd._lib import check, lib
+    R, C = 70, 130
+    g = _gene(bc)
+    x = W.uniform_x(R, C, T + 3 * S)
+    nseg = -(-T // S)
+    rng = np.random.default_rng(T * S)
+    lam0 = rng.standard_normal((R, C)).astype(np.float32)
+    mu0 = rng.standard_normal((R, C)).astype(np.float32)
+    sim = _sim(x, g, bc)
+    ckpt = torch.empty((nseg, 2, R, C), device="cuda")
+    sim.step_checkpoints(T, S, ckpt)
+    lam = torch.from_numpy(lam0).cuda()
+    mu = torch.from_numpy(mu0).cuda()
+    dth = torch.zeros(8, dtype=torch.float64, device="cuda")
+    work = torch.full((2 * (min(S, T) + 1), 2, R, C), float("nan"), device="cuda")
+    print(f"case step_bwd_ckpt {bc} T={T} S={S}", flush=True)
+    check(lib.rdcnn_step_bwd_ckpt(sim._h, ckpt.data_ptr(), T, S, work.data_ptr(), lam.data_ptr(),
+                                  mu.data_ptr(), dth.data_ptr()))
+    got_l, got_m, got_p = lam.cpu().numpy(), mu.cpu().numpy(), dth.cpu().numpy()
+    # serial reference: the same passes, segment by segment, one stream
+    lam2 = torch.from_numpy(lam0).cuda()
+    mu2 = torch.from_numpy(mu0).cuda()
+    dth2 = torch.zeros(8, dtype=torch.float64, device="cuda")
+    seg = torch.empty((min(S, T) + 1, 2, R, C), device="cuda")
+    for k in range(nseg - 1, -1, -1):
+        L = min(S, T - k * S)
+        sim.write_state_packed(ckpt[k])
+        sim.step_record_sparse(L, seg)
+        sim.step_bwd(seg, L, lam2, mu2, dth2)
+    assert np.array_equal(got_l, lam2.cpu().numpy()) and np.array_equal(got_m, mu2.cpu().numpy())
+    ref_p = dth2.cpu().numpy()
+    assert np.abs(got_p - ref_p).max() <= 1e-12 * np.abs(ref_p).max()
+    sim.close()
+    l0, m0, dp, _, _ = oracle.grad(x, x, g, bc, T, lam0, mu0, traj="f32")
+    assert _rel(got_l, l0) < 1e-4 and _rel(got_m, m0) < 1e-4, (_rel(got_l, l0), _rel(got_m, m0))
+    scale = max(abs(v) for v in dp.values())
+    for i, k in enumerate(KEYS):
+        assert abs(got_p[i] - dp[k]) <= 1e-3 * max(abs(dp[k]), 1e-3 * scale), (k, got_p[i], dp[k])
+
+
+def test_step_bwd_ckpt_rejects_bad_arguments():
+    from paper_2102_10340_amd._lib import EINVAL, lib
+    R, C, T, S = 16, 20, 12, 4
+    sim = _sim(W.uniform_x(R, C, 1), W.PLAIN_GENE, "zeroflux")
+    ckpt = torch.zeros((3, 2, R, C), device="cuda")
+    work = torch.zeros((2 * (S + 1), 2, R, C), device="cuda")
+    lam = torch.zeros((R, C), device="cuda")
+    mu = torch.zeros((R, C), device="cuda")
+    dth = torch.zeros(8, dtype=torch.float64, device="cuda")
+    f = lib.rdcnn_step_bwd_ckpt
+    assert f(sim._h, ckpt.data_ptr(), T, 0, work.data_ptr(), lam.data_ptr(), mu.data_ptr(),
+             dth.data_ptr()) == EINVAL                                  # S < 1
+    assert f(sim._h, ckpt.data_ptr(), -1, S, work.data_ptr(), lam.data_ptr(), mu.data_ptr(),
+             dth.data_ptr()) == EINVAL                                  # T < 0
+    assert f(sim._h, ckpt.data_ptr(), T, S, work.data_ptr(), lam.data_ptr(), lam.data_ptr(),
+             dth.data_ptr()) == EINVAL                                  # lam == mu
+    assert f(sim._h, ckpt.data_ptr(), T, S, work.data_ptr(), work[3, 0].data_ptr(),
+             mu.data_ptr(), dth.data_ptr()) == EINVAL                   # lam inside the workspace
+    assert f(sim._h, ckpt.data_ptr(), T, S, ckpt.data_ptr(), lam.data_ptr(), mu.data_ptr(),
+             dth.data_ptr()) == EINVAL                                  # workspace over checkpoints
+    assert f(sim._h, ckpt.data_ptr(), 0, S, None, None, None, None) == 0  # T = 0: nothing to do
     sim.close()
 
 
