@@ -153,12 +153,13 @@ def bench_fwd_bwd(stream):
             "ratio_fwd_bwd_to_fwd": t_sq / tf}
 
 
-def bench_batched(stream, per_class=4):
+def bench_batched(stream, per_class=8):
     """Parameter sweep: 1024 instances, side uniform over {128,256,512,1024},
     Du ~ U[0.01,0.2], Dv ~ U[0.2,1], epsilon ~ U[0.02,0.2], zero-flux, x ~ U[-1,1]
     per instance, T = 5000, one graph launch.  Baseline: the same instances run
-    one at a time (rdcnn_step(T) on one stream, default pass settings), timed on
-    `per_class` instances of each size and scaled by the class counts.  Both
+    one at a time (rdcnn_step(T) on one stream, each size with the autotuner's
+    cached single-grid shape), timed on `per_class` instances of each size and
+    scaled by the class counts.  Both
     sides are timed on steps T..2T (after an untimed first T steps, which also
     captures the batch's graph), and the sampled instances are compared bit for
     bit between the two."""
@@ -168,17 +169,19 @@ def bench_batched(stream, per_class=4):
     inst = W.sweep_instances(1024, 0)
     xs = [torch.from_numpy(W.uniform_x(d["rows"], d["cols"], d["seed"])).cuda() for d in inst]
     b = Batch(xs, [d["gene"] for d in inst], "zeroflux")
+    batch_from = b.tuned_from or "library default"
     b.use_graph(True)
     b.step(T)  # captures the T-step graph and runs it once (untimed)
     tb = _timed(lambda: b.step(T), stream)  # graph replay: steps T..2T
     cells = sum(d["rows"] * d["cols"] for d in inst)
     # per-instance baseline on a sample of each size class
-    t_single, same = 0.0, True
+    t_single, same, single_from = 0.0, True, {}
     for side in (128, 256, 512, 1024):
         idx = [i for i, d in enumerate(inst) if d["rows"] == side]
         ts = []
         for i in idx[:per_class]:
             sim = Simulation(xs[i], inst[i]["gene"], "zeroflux")
+            single_from[side] = sim.tuned_from or "library default"
             sim.step(T)
             ts.append(_timed(lambda: sim.step(T), stream))
             same &= bool(torch.equal(sim.state(), b.state(i)))
@@ -190,7 +193,8 @@ def bench_batched(stream, per_class=4):
             "batched_gcells": cells * T / tb / 1e9, "batched_s": tb,
             "per_instance_gcells": cells * T / t_single / 1e9, "per_instance_s_est": t_single,
             "speedup_vs_per_instance": t_single / tb, "sampled_instances_bitwise_equal": same,
-            "baseline_sample": f"{per_class} instances per size class, scaled by class counts"}
+            "baseline_sample": f"{per_class} instances per size class, scaled by class counts",
+            "pass_shape_from": {"batch": batch_from, "per_instance": single_from}}
 
 
 def bench_small_batch(stream, per_instance_sample=8):
@@ -577,7 +581,6 @@ def main():
         del a, b
     x = torch.from_numpy(W.centre_patch_x(R, C, 16, 0)).to(dev)
     chunk = args.chunk
-    depth = 8  # steps per pass of the default kernel on this shape
     snaps = torch.empty((args.steps + 1, 2, R, C), dtype=torch.float32, device=dev)
 
     warm = Simulation(x, W.PLAIN_GENE, "zeroflux", 1.0)
@@ -588,6 +591,8 @@ def main():
 
     # The timed job starts from the initial state; snapshot 0 is s_0.
     sim = Simulation(x, W.PLAIN_GENE, "zeroflux", 1.0)
+    shape = sim.pass_config()  # the autotuner's cached shape for 4096^2, else the library's
+    depth, cpl = shape["depth"], shape["cols_per_lane"]
     check(lib.rdcnn_read(sim._h, snaps[0, 0].data_ptr(), snaps[0, 1].data_ptr(), 0))
     torch.cuda.synchronize()
 
@@ -610,7 +615,7 @@ def main():
     tflops = FLOPS_PER_CELL_UPDATE * cells_per_launch / launch_s / 1e12
     eff_gbs = BYTES_PER_CELL_UPDATE * cells_per_launch / launch_s / 1e9
     alive = float(snaps[-1, 0].abs().max())
-    traffic = measured_traffic(f"void rd::stream_step_kernel<4, {depth}, 0>")
+    traffic = measured_traffic(f"void rd::stream_step_kernel<{cpl}, {depth}, 0>")
     pass_min = 16 * R * C  # one read and one write of the state per pass
 
     out = {
@@ -629,7 +634,9 @@ def main():
         "config": {"workload": "slow-growth 4096x4096 zero-flux, 16x16 random centre patch, "
                                "dt=0.1 Du=0.05 Dv=1 f1=u-u^3-v f2=0.1(u-v), T=10000 per step + "
                                "device snapshot", "time_steps_per_step": chunk,
-                   "grid": [R, C], "kernel": f"stream_step_kernel<4,{depth},0>",
+                   "grid": [R, C], "kernel": f"stream_step_kernel<{cpl},{depth},0>",
+                   "pass_shape": shape,
+                   "pass_shape_from": sim.tuned_from or "library default",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS, "traffic": traffic,

@@ -449,6 +449,18 @@ int rdcnn_batch_set_check_finite(rdcnn_batch_t b, int on);
 int rdcnn_batch_set_kernel(rdcnn_batch_t b, int depth, int cols_per_lane, int seg_rows);
 
 /*
+ * rdcnn_batch_set_class_seg_rows -- rows per tile for every instance of size
+ * rows x cols (a size class) in later plain steps (rdcnn_batch_step), in place
+ * of the batch-wide seg_rows; 0 returns the class to it.  Steps per pass and
+ * columns per lane stay batch-wide: one launch covers every class, so each
+ * pass mixes all classes' tiles (longest first) in one grid.  The paper tunes
+ * block and grid shapes by hand per run (Sec. II.B); the autotuner picks a
+ * height per class with this.  Results are bit-identical for every setting.
+ * Errors: RDCNN_EINVAL (seg_rows < 0, or no instance of that size).
+ */
+int rdcnn_batch_set_class_seg_rows(rdcnn_batch_t b, int rows, int cols, int seg_rows);
+
+/*
  * rdcnn_batch_use_graph -- on != 0: rdcnn_batch_step captures the launches of a
  * T-step run into a HIP graph on first use and replays it afterwards (one graph
  * launch per call).  Needs a non-default stream.  Errors: RDCNN_EINVAL.

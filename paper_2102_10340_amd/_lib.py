@@ -75,6 +75,7 @@ _SIGS = {
     "rdcnn_batch_set_check_finite": [_P, _I],
     "rdcnn_batch_set_shared_grad": [_P, _I],
     "rdcnn_batch_set_kernel": [_P, _I, _I, _I],
+    "rdcnn_batch_set_class_seg_rows": [_P, _I, _I, _I],
     "rdcnn_batch_use_graph": [_P, _I],
     "rdcnn_batch_use_lds": [_P, _I],
     "rdcnn_batch_lds_instances": [_P, ctypes.POINTER(ctypes.c_int)],

@@ -34,7 +34,9 @@ class Batch:
     sizes) and one gene per instance; shared boundary rule and k_a.  The states
     live in two packed [total] float32 buffers; ``state(i)`` views instance i."""
 
-    def __init__(self, xs, genes, bc: str = "zeroflux", ka: float = 1.0):
+    def __init__(self, xs, genes, bc: str = "zeroflux", ka: float = 1.0, tuned: bool = True):
+        """tuned: take the pass shape the autotuner cached for this exact mix of
+        sizes (tune.py, tuned.json), if there is one; else the library's."""
         if len(xs) != len(genes) or not xs:
             raise ValueError("need one gene per instance and at least one instance")
         self.device = xs[0].device
@@ -62,6 +64,10 @@ class Batch:
                                          self._x.data_ptr(), cxoff, float(ka),
                                          self.buf[0].data_ptr(), self.buf[1].data_ptr(),
                                          self.total, _stream_handle(self.device)))
+        self.tuned_from = None  # tuned.json key of the applied pass shape, if any
+        if tuned:
+            from . import tune
+            self.tuned_from = tune.apply(self)
 
     def __len__(self):
         return len(self.shapes)
@@ -72,6 +78,10 @@ class Batch:
 
     def set_kernel(self, depth: int = 0, cols_per_lane: int = 0, seg_rows: int = 0) -> None:
         check(lib.rdcnn_batch_set_kernel(self._h, int(depth), int(cols_per_lane), int(seg_rows)))
+
+    def set_class_seg_rows(self, rows: int, cols: int, seg_rows: int) -> None:
+        """Rows per tile for every instance of size rows x cols (0: the batch-wide value)."""
+        check(lib.rdcnn_batch_set_class_seg_rows(self._h, int(rows), int(cols), int(seg_rows)))
 
     def use_lds(self, on: bool = True) -> None:
         """Run instances that fit one workgroup's LDS whole, all steps in one launch."""

@@ -186,6 +186,7 @@ struct rdcnn_batch {
     int *lds_ids_dev;           // their indices
     int lds_count, lds_frame;   // how many, largest frame
     std::vector<int> R, C;
+    std::vector<int> seg_of;    // per-instance rows per tile of plain passes (0: the batch's)
     std::vector<long long> off;
     std::vector<rd::Gene> g;
     float *buf[2];
@@ -334,10 +335,11 @@ void batch_config(const rdcnn_batch *b, int *cpl, int *depth, int *seg)
 }
 
 // Tile list for one pass depth: every instance (but those run in LDS, if
-// skip_lds) cut into strips of wout output columns and segments of `seg` rows,
-// longest tiles first.
+// skip_lds) cut into strips of wout output columns and segments of `seg` rows
+// (with class_seg, an instance's own rows per tile where one was set for its
+// size class), longest tiles first.
 int build_tiles(const rdcnn_batch *b, int cpl, int depth, int seg, bool skip_lds,
-                std::vector<rd::BatchTile> &tiles)
+                std::vector<rd::BatchTile> &tiles, bool class_seg = false)
 {
     const int kpad = (depth + cpl - 1) / cpl * cpl;
     const int wout = 64 * cpl - 2 * kpad;
@@ -346,7 +348,8 @@ int build_tiles(const rdcnn_batch *b, int cpl, int depth, int seg, bool skip_lds
     for (int i = 0; i < b->n; ++i) {
         if (skip_lds && b->in_lds[i]) continue;
         const int R = b->R[i], C = b->C[i];
-        const int h = seg < R ? seg : R;
+        const int si = class_seg && b->seg_of[i] > 0 ? b->seg_of[i] : seg;
+        const int h = si < R ? si : R;
         for (int sx = 0; sx * wout < C; ++sx)
             for (int y0 = 0; y0 < R; y0 += h) {
                 rd::BatchTile t;
@@ -384,7 +387,7 @@ int upload_tiles(const std::vector<rd::BatchTile> &tiles, int depth, TileTable &
 
 // The table of `depth` in a set (built on first use).
 int table_in(rdcnn_batch *b, std::vector<TileTable> &set, int cpl, int depth, int seg,
-             bool skip_lds, const TileTable **out)
+             bool skip_lds, const TileTable **out, bool class_seg = false)
 {
     for (const TileTable &t : set)
         if (t.depth == depth) {
@@ -392,7 +395,7 @@ int table_in(rdcnn_batch *b, std::vector<TileTable> &set, int cpl, int depth, in
             return RDCNN_OK;
         }
     std::vector<rd::BatchTile> tiles;
-    int rc = build_tiles(b, cpl, depth, seg, skip_lds, tiles);
+    int rc = build_tiles(b, cpl, depth, seg, skip_lds, tiles, class_seg);
     if (rc != RDCNN_OK) return rc;
     TileTable t;
     rc = upload_tiles(tiles, depth, t);
@@ -404,7 +407,7 @@ int table_in(rdcnn_batch *b, std::vector<TileTable> &set, int cpl, int depth, in
 
 int table_for(rdcnn_batch *b, int cpl, int depth, int seg, const TileTable **out)
 {
-    return table_in(b, b->tables, cpl, depth, seg, true, out);
+    return table_in(b, b->tables, cpl, depth, seg, true, out, true);
 }
 
 void free_adj(rdcnn_batch *b)
@@ -573,6 +576,7 @@ int rdcnn_batch_create(rdcnn_batch_t *out, int n, const int *rows, const int *co
     b->bc = bc;
     b->R.assign(rows, rows + n);
     b->C.assign(cols, cols + n);
+    b->seg_of.assign(n, 0);
     b->off.assign(offsets, offsets + n);
     b->g.resize(n);
     std::vector<rd::BatchInst> inst(n);
@@ -930,6 +934,24 @@ int rdcnn_batch_set_kernel(rdcnn_batch_t b, int depth, int cols_per_lane, int se
         b->depth = depth;
         b->seg_rows = seg_rows;
     }
+    free_tables(b);
+    drop_graph(b);
+    return RDCNN_OK;
+}
+
+int rdcnn_batch_set_class_seg_rows(rdcnn_batch_t b, int rows, int cols, int seg_rows)
+{
+    if (!b) return bfail(RDCNN_EINVAL, "rdcnn_batch_set_class_seg_rows: NULL handle");
+    if (seg_rows < 0) return bfail(RDCNN_EINVAL, "rdcnn_batch_set_class_seg_rows: seg_rows < 0");
+    int hits = 0;
+    for (int i = 0; i < b->n; ++i)
+        if (b->R[i] == rows && b->C[i] == cols) {
+            b->seg_of[i] = seg_rows;
+            ++hits;
+        }
+    if (!hits)
+        return bfail(RDCNN_EINVAL, "rdcnn_batch_set_class_seg_rows: no instance of size %dx%d",
+                     rows, cols);
     free_tables(b);
     drop_graph(b);
     return RDCNN_OK;

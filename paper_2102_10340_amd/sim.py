@@ -25,7 +25,12 @@ class Simulation:
     "periodic" / "zeroflux".  The state lives in two caller-owned [2, R, C]
     buffers (u plane, v plane) that ping-pong between steps."""
 
-    def __init__(self, x: torch.Tensor, gene, bc: str = "zeroflux", ka: float = 1.0):
+    def __init__(self, x: torch.Tensor, gene, bc: str = "zeroflux", ka: float = 1.0,
+                 tuned: bool = True):
+        """tuned: take the forward pass shape the autotuner cached for this grid
+        size and boundary rule (tune.py, tuned.json), if there is one; else the
+        library's automatic one.  The setting also applies to the recording
+        calls (capped to what they support)."""
         if x.dim() != 2 or x.dtype != torch.float32 or not x.is_cuda:
             raise ValueError("x must be a 2-D float32 CUDA tensor")
         self.device = x.device
@@ -42,6 +47,10 @@ class Simulation:
                                    ctypes.byref(self._params), self._x.data_ptr(), float(ka),
                                    self.buf[0].data_ptr(), self.buf[1].data_ptr(),
                                    _stream_handle(self.device)))
+        self.tuned_from = None  # tuned.json key of the applied pass shape, if any
+        if tuned:
+            from . import tune
+            self.tuned_from = tune.apply(self, modes=("forward",))
 
     MODELS = {"fitzhugh_nagumo": 0, "gray_scott": 1, "cnn": 2}
 
@@ -82,9 +91,10 @@ class Simulation:
         return cls.model("cnn", x0, image, [dt] + a + b + [float(z)], bc)
 
     @classmethod
-    def from_state(cls, u0: torch.Tensor, v0: torch.Tensor, gene, bc: str = "zeroflux"):
+    def from_state(cls, u0: torch.Tensor, v0: torch.Tensor, gene, bc: str = "zeroflux",
+                   tuned: bool = True):
         """A grid whose state starts at (u0, v0) instead of k_a x."""
-        sim = cls(u0, gene, bc, 1.0)
+        sim = cls(u0, gene, bc, 1.0, tuned)
         sim.write_state(u0, v0)
         return sim
 

@@ -10,12 +10,17 @@ candidate settings
     cols_per_lane  1, 2 or 4 adjacent columns per lane (strip = 64 * cols)
     seg_rows       output rows per wavefront (0 = the library's choice)
 
-with HIP events on the current stream and keeps the fastest.  Every setting
-gives bit-identical states (the forward) or the same adjoint up to float32
-summation order, so tuning only changes speed.  Results are cached in a JSON
-file keyed by GPU architecture, mode, size and boundary rule; ``apply`` sets a
-cached choice on a Simulation (for plain runs, or for the even recording and
-paired adjoint that gradients use) or a Batch.
+with HIP events on the current stream and keeps the fastest.  For a batch it
+then times, one size class at a time (largest total cells first), the rows
+per tile of that class with the others fixed (rdcnn_batch_set_class_seg_rows):
+steps per pass and columns per lane are per launch, and one launch covers
+every class.  Every setting gives bit-identical states (the forward) or the
+same adjoint up to float32 summation order, so tuning only changes speed.
+Results are cached in a JSON file keyed by GPU architecture, mode, size and
+boundary rule; ``apply`` sets a cached choice on a Simulation (for plain runs,
+or for the even recording and paired adjoint that gradients use) or a Batch.
+Simulation and Batch apply the cached forward / batch entry themselves when
+constructed (``tuned=True``).
 
 The package ships ``tuned.json`` with results measured on an MI355X for the
 benchmark shapes; ``RDCNN_TUNE_CACHE`` names another file.
@@ -140,7 +145,7 @@ def tune(mode: str, rows: int, cols: int, bc: str = "zeroflux", gene=None, budge
     run = _timer(stream)
     gen = torch.Generator(device="cuda").manual_seed(0)
     x = torch.rand((rows, cols), generator=gen, device="cuda", dtype=torch.float32) * 2 - 1
-    sim = Simulation(x, gene, bc)
+    sim = Simulation(x, gene, bc, tuned=False)
     T = _steps_for(rows * cols)
     results = {}
     t_end = time.time() + budget_s
@@ -189,9 +194,9 @@ def tune_batch(xs, genes, bc: str = "zeroflux", steps: int = 240, budget_s: floa
     from .batch import Batch
     stream = torch.cuda.current_stream()
     run = _timer(stream)
-    b = Batch(xs, genes, bc)
+    b = Batch(xs, genes, bc, tuned=False)
     cells = sum(int(x.numel()) for x in xs)
-    shapes = [tuple(x.shape) for x in xs]
+    shapes = [tuple(int(v) for v in x.shape) for x in xs]
     side = int(np.sqrt(max(r * c for r, c in shapes)))
     results = {}
     t_end = time.time() + budget_s
@@ -203,12 +208,34 @@ def tune_batch(xs, genes, bc: str = "zeroflux", steps: int = 240, budget_s: floa
         results[cand] = cells * steps / t / 1e9
         if verbose:
             print("batch", cand, f"{results[cand]:.1f} Gcell/s", flush=True)
-    b.close()
     best = max(results, key=results.get)
+    b.set_kernel(*best)
+    # rows per tile per size class, largest classes first, the others held
+    counts = {}
+    for r, c in shapes:
+        counts[(r, c)] = counts.get((r, c), 0) + 1
+    rate = results[best]
+    class_seg = {}
+    for (r, c) in sorted(counts, key=lambda k: -counts[k] * k[0] * k[1]):
+        keep = 0
+        for h in (16, 32, 64, 128, 256, 512):
+            if h > r or h == best[2]:
+                continue
+            b.set_class_seg_rows(r, c, h)
+            g = cells * steps / run(lambda: b.step(steps)) / 1e9
+            if verbose:
+                print("batch class", (r, c), "rows", h, f"{g:.1f} Gcell/s", flush=True)
+            if g > rate * 1.01:  # keep a class height only for a clear gain
+                keep, rate = h, g
+        b.set_class_seg_rows(r, c, keep)
+        if keep:
+            class_seg[f"{r}x{c}"] = keep
+    b.close()
     if write:
         save({batch_key(shapes, bc): {"depth": best[0], "cols_per_lane": best[1],
-                                      "seg_rows": best[2], "gcells": results[best]}})
-    return best, results
+                                      "seg_rows": best[2], "class_seg_rows": class_seg,
+                                      "gcells": rate}})
+    return best, dict(results, class_seg_rows=class_seg, gcells=rate)
 
 
 def lookup(k: str, path: str = None):
@@ -216,28 +243,42 @@ def lookup(k: str, path: str = None):
     return None if e is None else (e["depth"], e["cols_per_lane"], e["seg_rows"])
 
 
-def apply(obj, path: str = None, grad: bool = False) -> bool:
-    """Set the cached settings (if any) on a Simulation or a Batch; returns True
-    if something was applied.  For a Simulation, grad=False takes the "forward"
-    and "adjoint" entries, grad=True the "record_even" and "adjoint_even" ones
-    (what a gradient run uses)."""
+def apply(obj, path: str = None, grad: bool = False, modes=None):
+    """Set the cached settings (if any) on a Simulation or a Batch; returns the
+    cache key(s) applied ("+"-joined), or None.  For a Simulation, grad=False
+    takes the "forward" and "adjoint" entries, grad=True the "record_even" and
+    "adjoint_even" ones (what a gradient run uses); `modes` restricts that to
+    the named ones.  A Batch takes its size mix's entry, with the rows per tile
+    of each size class the tuner kept."""
     from .batch import Batch
-    done = False
+    if _arch() == "unknown":
+        return None
     if isinstance(obj, Batch):
-        cfg = lookup(batch_key(obj.shapes, obj.bc), path)
-        if cfg:
-            obj.set_kernel(*cfg)
-            done = True
-        return done
-    cfg = lookup(key("record_even" if grad else "forward", obj.rows, obj.cols, obj.bc), path)
-    if cfg:
-        obj.set_kernel(2, *cfg)
-        done = True
-    cfg = lookup(key("adjoint_even" if grad else "adjoint", obj.rows, obj.cols, obj.bc), path)
-    if cfg:
-        obj.set_adjoint_kernel(*cfg)
-        done = True
-    return done
+        k = batch_key(obj.shapes, obj.bc)
+        e = load(path).get(k)
+        if e is None:
+            return None
+        obj.set_kernel(e["depth"], e["cols_per_lane"], e["seg_rows"])
+        present = set(obj.shapes)
+        for cls, h in e.get("class_seg_rows", {}).items():
+            r, c = (int(v) for v in cls.split("x"))
+            if (r, c) in present:
+                obj.set_class_seg_rows(r, c, int(h))
+        return k
+    done = []
+    for mode in (("record_even", "adjoint_even") if grad else ("forward", "adjoint")):
+        if modes is not None and mode not in modes:
+            continue
+        k = key(mode, obj.rows, obj.cols, obj.bc)
+        cfg = lookup(k, path)
+        if not cfg:
+            continue
+        if mode in ("forward", "record_even"):
+            obj.set_kernel(2, *cfg)
+        else:
+            obj.set_adjoint_kernel(*cfg)
+        done.append(k)
+    return "+".join(done) if done else None
 
 
 if __name__ == "__main__":
@@ -247,7 +288,7 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser(description="tune pass shapes and update the cache")
     ap.add_argument("--mode", default="forward",
                     choices=["forward", "record", "record_even", "adjoint", "adjoint_even",
-                             "batch-sweep"])
+                             "batch-sweep", "bench"])
     ap.add_argument("--size", type=int, nargs="+", default=[4096, 1024, 256])
     ap.add_argument("--bc", default="zeroflux")
     ap.add_argument("--budget", type=float, default=60.0)
@@ -255,6 +296,14 @@ if __name__ == "__main__":
     a = ap.parse_args()
     if a.cache:
         os.environ["RDCNN_TUNE_CACHE"] = a.cache
+    if a.mode == "bench":
+        # the shapes the benchmark runs: the forward of every grid side it times
+        # one at a time (headline, differentiation, per-instance baselines) and
+        # the 1024-instance parameter-sweep mix
+        for n in (4096, 1024, 512, 256, 128):
+            best, res = tune("forward", n, n, a.bc, budget_s=a.budget)
+            print("forward", n, "best", best, f"{res[best]:.1f} Gcell/s", flush=True)
+        a.mode = "batch-sweep"
     if a.mode == "batch-sweep":
         # the 1024-instance parameter-sweep workload (seeded synthetic inputs)
         import workloads as W
@@ -263,7 +312,8 @@ if __name__ == "__main__":
         s = torch.cuda.Stream()
         with torch.cuda.stream(s):
             best, res = tune_batch(xs, [d["gene"] for d in inst], a.bc, budget_s=a.budget)
-        print("batch-sweep best", best, f"{res[best]:.1f} Gcell/s", flush=True)
+        print("batch-sweep best", best, "class rows", res["class_seg_rows"],
+              f"{res['gcells']:.1f} Gcell/s", flush=True)
     else:
         for n in a.size:
             best, res = tune(a.mode, n, n, a.bc, budget_s=a.budget)

@@ -219,15 +219,25 @@ def _assert_full_grid(got, want, what, tol=None):
         assert np.abs(got[0] - want[0]).max() <= tol and np.abs(got[1] - want[1]).max() <= tol
 
 
-def _default_kernel_is_headline():
-    """The automatic pass shape of a 4096^2 grid is four columns per lane and
-    eight steps per pass (the shape whose strips inside the grid take the
-    16-byte vector loads and unmapped row offsets)."""
+def _headline_kernels():
+    """The pass shapes to check at 4096^2: the one the benchmark's Simulation
+    takes (the autotuner's cached shape, else the library's automatic one) and
+    the library's automatic one, four columns per lane and eight steps per
+    pass (the shape whose strips inside the grid take the 16-byte vector loads
+    and unmapped row offsets), once if they are the same."""
     from paper_2102_10340_amd import Simulation
-    sim = Simulation(torch.zeros((4096, 4096), device="cuda"), W.PLAIN_GENE, "zeroflux")
-    cfg = sim.pass_config()
-    sim.close()
-    assert (cfg["cols_per_lane"], cfg["depth"]) == (4, 8), cfg
+    out = []
+    for tuned in (True, False):
+        sim = Simulation(torch.zeros((4096, 4096), device="cuda"), W.PLAIN_GENE, "zeroflux",
+                         tuned=tuned)
+        cfg = sim.pass_config()
+        sim.close()
+        if not tuned:
+            assert (cfg["cols_per_lane"], cfg["depth"]) == (4, 8), cfg
+        k = (2, cfg["depth"], cfg["cols_per_lane"], cfg["seg_rows"])
+        if k not in out:
+            out.append(k)
+    return out
 
 
 def test_slow_growth_headline_launch_whole_grid():
@@ -236,27 +246,32 @@ def test_slow_growth_headline_launch_whole_grid():
     1000 steps equals the float32 oracle's bit for bit (so within 1e-5 and
     1e-3), and the float64 oracle states the drift, asserted below its bar."""
     from paper_2102_10340_amd import Simulation
-    _default_kernel_is_headline()
+    kernels = _headline_kernels()
     R = C = 4096
     g = W.PLAIN_GENE
     x = W.centre_patch_x(R, C, 16, 0)
-    sim = Simulation(torch.from_numpy(x).cuda(), g, "zeroflux", 1.0)
+    sims = [Simulation(torch.from_numpy(x).cuda(), g, "zeroflux", 1.0, tuned=False)
+            for _ in kernels]
+    for sim, k in zip(sims, kernels):
+        sim.set_kernel(*k)
     u32, v32 = oracle.init_state(x, 1.0)
     u64, v64 = oracle.init_state(x, 1.0, np.float64)
     done = 0
     for T, tol in ((100, 1e-5), (1000, 1e-3)):
-        print(f"case slow-growth 4096^2 T={T}", flush=True)
-        sim.step(T - done)
-        got = sim.read_host()
         u32, v32 = oracle.run(u32, v32, g, "zeroflux", T - done, "f32")
-        _assert_full_grid(got, (u32, v32), f"slow growth T={T}", tol)
         u64, v64 = oracle.run(u64, v64, g, "zeroflux", T - done, "f64")
-        drift = max(np.abs(got[0] - u64).max(), np.abs(got[1] - v64).max())
-        print(f"slow growth T={T}: float32 vs float64 drift {drift:.3g}", flush=True)
-        assert drift <= SLOW_GROWTH_DRIFT_BAR[T], (T, drift)
+        for sim, k in zip(sims, kernels):
+            print(f"case slow-growth 4096^2 T={T} kernel {k}", flush=True)
+            sim.step(T - done)
+            got = sim.read_host()
+            _assert_full_grid(got, (u32, v32), f"slow growth T={T} {k}", tol)
+            drift = max(np.abs(got[0] - u64).max(), np.abs(got[1] - v64).max())
+            print(f"slow growth T={T}: float32 vs float64 drift {drift:.3g}", flush=True)
+            assert drift <= SLOW_GROWTH_DRIFT_BAR[T], (T, drift)
         done = T
     assert np.abs(got[0]).max() > 0.1  # the patch is alive
-    sim.close()
+    for sim in sims:
+        sim.close()
 
 
 @pytest.mark.parametrize("bc", BCS)
@@ -266,11 +281,12 @@ def test_random_grid_headline_launch_whole_grid(bc):
     carries live values: bitwise against the float32 oracle after 100 steps.
     Periodic uses the paper's gene (the Table I launch with a random image),
     zero-flux the plain gene."""
-    _default_kernel_is_headline()
     x = W.uniform_x(4096, 4096, 11)
     g = W.gene(W.PAPER_DEFAULT_GENE) if bc == "periodic" else W.PLAIN_GENE
-    print(f"case random 4096^2 {bc} T=100", flush=True)
-    _assert_full_grid(gpu_run(x, g, bc, 100), oracle_run(x, g, bc, 100), f"random 4096 {bc}", 1e-5)
+    want = oracle_run(x, g, bc, 100)
+    for k in _headline_kernels():
+        print(f"case random 4096^2 {bc} T=100 kernel {k}", flush=True)
+        _assert_full_grid(gpu_run(x, g, bc, 100, k), want, f"random 4096 {bc} {k}", 1e-5)
 
 
 def test_table1_launch_whole_grid():

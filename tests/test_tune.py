@@ -38,6 +38,9 @@ def test_shipped_cache_is_valid():
         mode = k.split("/")[1]
         lim = tune.MAX_ADJ_DEPTH if mode == "adjoint" else tune.MAX_DEPTH
         assert e["cols_per_lane"] in (1, 2, 4) and 1 <= e["depth"] <= lim[e["cols_per_lane"]], k
+        for cls, h in e.get("class_seg_rows", {}).items():  # per size class rows per tile
+            r, c = (int(v) for v in cls.split("x"))
+            assert mode == "batch" and f"{r}x{c}*" in k and h > 0, (k, cls)
 
 
 @pytest.mark.gpu
@@ -51,6 +54,7 @@ def test_tuned_settings_stay_bitwise(tmp_path, monkeypatch):
     assert best in res and all(v > 0 for v in res.values())
     x = W.uniform_x(96, 200, 2)
     sim = Simulation(torch.from_numpy(x).cuda(), W.PLAIN_GENE, "zeroflux")
+    assert sim.tuned_from == tune.key("forward", 96, 200, "zeroflux")  # applied on construction
     assert tune.apply(sim)
     sim.step(30)
     u, v = sim.read_host()
@@ -86,3 +90,37 @@ def test_tuned_gradient_settings_keep_the_adjoint(tmp_path, monkeypatch):
         out.append((st.clone(), adj))
         sim.close()
     assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+
+
+@pytest.mark.gpu
+def test_batch_class_tuning_stays_bitwise(tmp_path, monkeypatch):
+    """Tuning a mix of sizes picks a batch-wide shape and rows per tile per size
+    class; a Batch of that mix takes them on construction, and its states equal
+    an untuned batch's and the float32 oracle's bit for bit."""
+    import torch
+    import oracle
+    import workloads as W
+    from paper_2102_10340_amd import Batch, tune
+    monkeypatch.setenv("RDCNN_TUNE_CACHE", str(tmp_path / "t.json"))
+    shapes = [(300, 260), (300, 260), (160, 410), (520, 200), (300, 260)]
+    xs_np = [W.uniform_x(r, c, 11 + i) for i, (r, c) in enumerate(shapes)]
+    xs = [torch.from_numpy(x).cuda() for x in xs_np]
+    genes = [W.gene(Du=0.05 + 0.01 * i, Dv=0.5) for i in range(len(shapes))]
+    best, res = tune.tune_batch(xs, genes, "zeroflux", steps=24, budget_s=8.0)
+    e = tune.load()[tune.batch_key(shapes, "zeroflux")]
+    assert (e["depth"], e["cols_per_lane"], e["seg_rows"]) == best
+    assert set(e["class_seg_rows"]) <= {"300x260", "160x410", "520x200"}
+    tuned = Batch(xs, genes, "zeroflux")
+    assert tuned.tuned_from == tune.batch_key(shapes, "zeroflux")
+    plain = Batch(xs, genes, "zeroflux", tuned=False)
+    assert plain.tuned_from is None
+    T = 27
+    tuned.step(T)
+    plain.step(T)
+    for i, x in enumerate(xs_np):
+        assert torch.equal(tuned.state(i), plain.state(i)), i
+        ou, ov = oracle.run(*oracle.init_state(x, 1.0), genes[i], "zeroflux", T, "f32")
+        st = tuned.state(i).cpu().numpy()
+        assert np.array_equal(st[0], ou) and np.array_equal(st[1], ov), i
+    tuned.close()
+    plain.close()
