@@ -264,10 +264,11 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs A)
 // columns level 2p makes, which the strip's halo of KB columns already holds.
 // Boundary rows and columns are mapped as in the forward kernel, where the
 // mirror rule reproduces the zero-flux edge bit for bit.
-template <int CPL, int KB, bool FAST, bool ROWS_IN, bool LAMS, int DL, int DE>
+template <int CPL, int KB, bool FAST, bool ROWS_IN, bool LAMS, int DL, int DE, int NR>
 __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<CPL> &t)
 {
-    static_assert(KB % 2 == 0 && DL >= 1 && DL <= kFetchPast && DE >= 1 && DE <= 3, "pass shape");
+    static_assert(KB % 2 == 0 && NR % 3 == 0 && DL >= 1 && DL <= kFetchPast && DL <= NR - 3 &&
+                  DE >= 1 && DE <= NR - 3, "pass shape");
     constexpr int P = KB / 2;
     const int C = A.t.C, R = A.t.R, bc = A.t.bc;
     const unsigned pbytes = 4u * (unsigned)R * (unsigned)C;
@@ -289,16 +290,16 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
 #pragma unroll
     for (int e = 0; e < CPL; ++e) w[e] = FAST ? 1.0f : t.owns(A.t, e);
 
-    float l0[6][CPL], m0[6][CPL];          // level 0 ring
+    float l0[NR][CPL], m0[NR][CPL];        // level 0 ring
     float bl[KB][3][CPL], bm[KB][3][CPL];  // levels 1 .. KB-1 (index 0 unused)
-    float eu[P][6][CPL], ev[P][6][CPL];    // E_p rings
+    float eu[P][NR][CPL], ev[P][NR][CPL];  // E_p rings
     float acc[NSUM];
 #pragma unroll
     for (int k = 0; k < NSUM; ++k) acc[k] = 0.0f;
 #pragma unroll
     for (int e = 0; e < CPL; ++e) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
+        for (int q = 0; q < NR; ++q) {
             l0[q][e] = m0[q][e] = 0.0f;
 #pragma unroll
             for (int p = 0; p < P; ++p) eu[p][q][e] = ev[p][q][e] = 0.0f;
@@ -320,15 +321,17 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
 #pragma unroll
         for (int q = 0; q < DE; ++q)
             if (4 * p - DE + q < 0) {  // fetch iteration before the loop
+                // row rbase+2p+q, whose slot the loop's fetch at iteration
+                // 4p-DE+q would have filled: (4p + q) mod NR
                 const unsigned o = (unsigned)(P - 1 - p) * sstride + roff(rbase + 2 * p + q);
-                load_row<CPL, FAST>(sb, o, t, eu[p][q]);
-                load_row<CPL, FAST>(sb, o + pbytes, t, ev[p][q]);
+                load_row<CPL, FAST>(sb, o, t, eu[p][(4 * p + q) % NR]);
+                load_row<CPL, FAST>(sb, o + pbytes, t, ev[p][(4 * p + q) % NR]);
             }
 
     auto iteration = [&](const int it, const int S6) __attribute__((always_inline)) {
         const int S = S6 % 3;
         // ring slots of rows newest-2 (north), newest-1 (centre), newest (south)
-        const int qN = (S6 + 4) % 6, qC = (S6 + 5) % 6, qS = S6;
+        const int qN = (S6 + NR - 2) % NR, qC = (S6 + NR - 1) % NR, qS = S6;
         float tl[CPL], tm[CPL];
 #pragma unroll
         for (int i = 0; i < KB; ++i) {
@@ -392,14 +395,14 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
             // reads in this iteration.
             if (i == 0) {
                 const unsigned ro = roff(rbase + it + DL);
-                load_row<CPL, FAST>(il, ro, t, l0[(S6 + DL) % 6]);
-                load_row<CPL, FAST>(im, ro, t, m0[(S6 + DL) % 6]);
+                load_row<CPL, FAST>(il, ro, t, l0[(S6 + DL) % NR]);
+                load_row<CPL, FAST>(im, ro, t, m0[(S6 + DL) % NR]);
             }
             if (i % 2 == 1 && it + DE >= 4 * p && it + DE <= n_real - 1) {  // rows of E_p's range
                 const unsigned o =
                     (unsigned)(P - 1 - p) * sstride + roff(rbase + it - 2 * p + DE);
-                load_row<CPL, FAST>(sb, o, t, eu[p][(S6 + DE) % 6]);
-                load_row<CPL, FAST>(sb, o + pbytes, t, ev[p][(S6 + DE) % 6]);
+                load_row<CPL, FAST>(sb, o, t, eu[p][(S6 + DE) % NR]);
+                load_row<CPL, FAST>(sb, o + pbytes, t, ev[p][(S6 + DE) % NR]);
             }
         }
         const int m = rbase + it - KB;
@@ -412,18 +415,12 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
 
     // Iterations from n_real on would only fetch rows nobody reads: leave
     // the unrolled body as soon as the walk is done (uniform branches).
-    for (int it = 0; it < n_real; it += 6) {
-        iteration(it, 0);
-        if (it + 1 >= n_real) break;
-        iteration(it + 1, 1);
-        if (it + 2 >= n_real) break;
-        iteration(it + 2, 2);
-        if (it + 3 >= n_real) break;
-        iteration(it + 3, 3);
-        if (it + 4 >= n_real) break;
-        iteration(it + 4, 4);
-        if (it + 5 >= n_real) break;
-        iteration(it + 5, 5);
+    for (int it = 0; it < n_real; it += NR) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {  // fully unrolled: every slot index a constant
+            if (it + q >= n_real) break;
+            iteration(it + q, q);
+        }
     }
     add_tile_sums<CPL, FAST>(A, t, acc);
 }
@@ -431,9 +428,12 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
 // Fetch distances of the paired passes, in iterations.  Three iterations of
 // lead let the compiler's wait counts (which assume conditional fetches were
 // skipped) stay clear of the newest fetches; a sweep on 1024^2 put (3, 3)
-// ahead of (1, 3), (2, 3), (2, 2) and (3, 2).
+// ahead of (1, 3), (2, 3), (2, 2) and (3, 2).  Nine-slot rings with six
+// iterations of lead for the E_p rows (127 VGPRs, still four waves per SIMD)
+// measured the same (8.57 against 8.52 ms for 2000 steps on 1024^2).
 constexpr int kPairDL = 3;
 constexpr int kPairDE = 3;
+constexpr int kPairRing = 6;  // ring slots per row stream (a multiple of 3, >= 3 + fetch distance)
 
 template <int CPL, int KB, bool LAMS>
 __global__ __launch_bounds__(64) void adjoint_pair_kernel(AdjArgs A)
@@ -442,11 +442,11 @@ __global__ __launch_bounds__(64) void adjoint_pair_kernel(AdjArgs A)
     if (!t.init(A.t)) return;
     if (t.fast) {
         if (t.y0 >= KB && t.y1 + KB + kFetchPast <= A.t.R)
-            adjoint_pair_body<CPL, KB, true, true, LAMS, kPairDL, kPairDE>(A, t);
+            adjoint_pair_body<CPL, KB, true, true, LAMS, kPairDL, kPairDE, kPairRing>(A, t);
         else
-            adjoint_pair_body<CPL, KB, true, false, LAMS, kPairDL, kPairDE>(A, t);
+            adjoint_pair_body<CPL, KB, true, false, LAMS, kPairDL, kPairDE, kPairRing>(A, t);
     } else {
-        adjoint_pair_body<CPL, KB, false, false, LAMS, kPairDL, kPairDE>(A, t);
+        adjoint_pair_body<CPL, KB, false, false, LAMS, kPairDL, kPairDE, kPairRing>(A, t);
     }
 }
 
@@ -527,11 +527,11 @@ __global__ __launch_bounds__(64) void batch_adjoint_pair_kernel(BatchAdjArgs B)
     batch_tile_args<CPL>(B, id, A, t);
     if (t.fast) {
         if (t.y0 >= KB && t.y1 + KB + kFetchPast <= A.t.R)
-            adjoint_pair_body<CPL, KB, true, true, LAMS, kPairDL, kPairDE>(A, t);
+            adjoint_pair_body<CPL, KB, true, true, LAMS, kPairDL, kPairDE, kPairRing>(A, t);
         else
-            adjoint_pair_body<CPL, KB, true, false, LAMS, kPairDL, kPairDE>(A, t);
+            adjoint_pair_body<CPL, KB, true, false, LAMS, kPairDL, kPairDE, kPairRing>(A, t);
     } else {
-        adjoint_pair_body<CPL, KB, false, false, LAMS, kPairDL, kPairDE>(A, t);
+        adjoint_pair_body<CPL, KB, false, false, LAMS, kPairDL, kPairDE, kPairRing>(A, t);
     }
 }
 
