@@ -116,7 +116,7 @@ enum {
  * whose A template is not mirror symmetric runs one step per pass at a
  * zero-flux edge (blocked passes would not reproduce the edge-copy rule).
  * rdcnn_step, rdcnn_read, rdcnn_write_state, rdcnn_current, rdcnn_set_kernel
- * (kind 0 or 2) and rdcnn_destroy apply as for rdcnn_create's grids; models
+ * (kind 0, 2 or 3) and rdcnn_destroy apply as for rdcnn_create's grids; models
  * other than FitzHugh-Nagumo use passes of 1, 2, 4 or 8 steps and 1 or 2
  * columns per lane, and have no reverse pass (rdcnn_step_record,
  * rdcnn_adjoint and rdcnn_set_params return RDCNN_EINVAL for them).
@@ -183,7 +183,10 @@ int rdcnn_current(rdcnn_t h, float **state_dev);
  * rdcnn_set_kernel -- choose how later rdcnn_step calls run (testing and
  * tuning; the default is chosen per grid shape).
  *   kind 0: automatic; 1: one thread per cell, one launch per step (reference
- *   kernel); 2: register-streamed kernel doing up to `depth` steps per HBM pass.
+ *   kernel); 2: register-streamed kernel doing up to `depth` steps per HBM pass,
+ *   for every call that steps (the recording calls cap it to what they support);
+ *   3: as 2 for rdcnn_step and rdcnn_step_checkpoints only, the recording calls
+ *   keep their automatic shapes (what an autotuned forward shape wants).
  *   cols_per_lane 1 or 2 (depth 1..16) or 4 (depth 1..12); seg_rows: output rows
  *   per wavefront, 0 = automatic.  Other fields are ignored for kinds 0 and 1.
  *   Every setting gives bit-identical states.  Errors: RDCNN_EINVAL.

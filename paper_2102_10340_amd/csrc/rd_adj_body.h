@@ -281,7 +281,8 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
     const AdjConst kc(g);
     const int y0 = t.y0, y1 = t.y1;
     const int rbase = y0 - KB;
-    const int n_real = y1 - y0 + 2 * KB;
+    const int hrows = y1 - y0;  // output rows
+    const int n_real = hrows + 2 * KB;
     auto roff = [&](int r) -> unsigned {
         return ROWS_IN ? (unsigned)r * rowb : row_off(r, R, C, bc);
     };
@@ -347,7 +348,10 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
             const float *mC = i == 0 ? m0[qC] : bm[i][sl.cs];
             const float *mS = i == 0 ? m0[qS] : bm[i][sl.ns];
             const int m = rbase + it - i - 1;  // row made by level i+1
-            if (it >= 2 * i + 2 && it < n_real) {
+            // (every iteration of the walk has it < n_real; the tests below
+            // are single unsigned compares to keep the scalar unit, which
+            // serves a compute unit's four SIMDs, out of the way)
+            if (it >= 2 * i + 2) {
                 float u[CPL], v[CPL];  // the state level i steps back with, row m
                 if (i % 2 == 0) {
                     // O_p row m from E_p rows m-1, m, m+1
@@ -373,7 +377,7 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
                 const float rl = from_right_lane(lC[0]);
                 const float lm = from_left_lane(mC[CPL - 1]);
                 const float rm = from_right_lane(mC[0]);
-                const int count = m >= y0 && m < y1;
+                const int count = (unsigned)(m - y0) < (unsigned)hrows;
 #pragma unroll
                 for (int e = 0; e < CPL; ++e) {
                     const float lW = e == 0 ? ll : lC[e - 1];
@@ -398,7 +402,8 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
                 load_row<CPL, FAST>(il, ro, t, l0[(S6 + DL) % NR]);
                 load_row<CPL, FAST>(im, ro, t, m0[(S6 + DL) % NR]);
             }
-            if (i % 2 == 1 && it + DE >= 4 * p && it + DE <= n_real - 1) {  // rows of E_p's range
+            // rows of E_p's range: 4p <= it + DE <= n_real - 1
+            if (i % 2 == 1 && (unsigned)(it + DE - 4 * p) <= (unsigned)(n_real - 1 - 4 * p)) {
                 const unsigned o =
                     (unsigned)(P - 1 - p) * sstride + roff(rbase + it - 2 * p + DE);
                 load_row<CPL, FAST>(sb, o, t, eu[p][(S6 + DE) % NR]);
@@ -406,7 +411,7 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
             }
         }
         const int m = rbase + it - KB;
-        if (m >= y0 && m < y1) {
+        if ((unsigned)(m - y0) < (unsigned)hrows) {
             const unsigned o = 4u * (unsigned)m * C;
             store_row<CPL, FAST>(ol, o, C, t, tl);
             store_row<CPL, FAST>(om, o, C, t, tm);

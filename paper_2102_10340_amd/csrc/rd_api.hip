@@ -392,6 +392,7 @@ int run_steps(rdcnn_sim *h, long long n, float *rec, bool rec_even = false, int 
     }
     long long q = 0;
     int kind = h->kind, cpl = h->cpl, depth = h->depth, seg = h->seg_rows;
+    if (kind == 3) kind = rec ? 0 : 2;  // forced shape for plain steps only
     if (kind == 0) {
         kind = 2;
         auto_config(h, &cpl, &depth, &seg, rec != nullptr, rec_even);
@@ -955,7 +956,7 @@ int rdcnn_step_checkpoints(rdcnn_t h, long long T, long long S, float *ckpt_dev)
                 return fail(RDCNN_EINVAL, "%s: checkpoint buffer overlaps a state buffer", who);
         }
     }
-    int kind = h->kind, cpl = h->cpl, depth = h->depth, seg = h->seg_rows;
+    int kind = h->kind == 3 ? 2 : h->kind, cpl = h->cpl, depth = h->depth, seg = h->seg_rows;
     if (kind == 0) {
         kind = 2;
         auto_config(h, &cpl, &depth, &seg, false);
@@ -1196,14 +1197,14 @@ int rdcnn_set_kernel(rdcnn_t h, int kind, int depth, int cols_per_lane, int seg_
         h->kind = kind;
         return RDCNN_OK;
     }
-    if (kind != 2) return fail(RDCNN_EINVAL, "rdcnn_set_kernel: unknown kind %d", kind);
+    if (kind != 2 && kind != 3) return fail(RDCNN_EINVAL, "rdcnn_set_kernel: unknown kind %d", kind);
     if (cols_per_lane != 1 && cols_per_lane != 2 && cols_per_lane != 4)
         return fail(RDCNN_EINVAL, "rdcnn_set_kernel: cols_per_lane %d not in {1,2,4}", cols_per_lane);
     if (depth < 1 || depth > rd::max_depth(cols_per_lane))
         return fail(RDCNN_EINVAL, "rdcnn_set_kernel: depth %d out of range for cols_per_lane %d",
                     depth, cols_per_lane);
     if (seg_rows < 0) return fail(RDCNN_EINVAL, "rdcnn_set_kernel: seg_rows < 0");
-    h->kind = 2;
+    h->kind = kind;
     h->depth = depth;
     h->cpl = cols_per_lane;
     h->seg_rows = seg_rows;
@@ -1214,7 +1215,7 @@ int rdcnn_pass_config(rdcnn_t h, int *kind, int *depth, int *cols_per_lane, int 
 {
     if (!h || !kind || !depth || !cols_per_lane || !seg_rows)
         return fail(RDCNN_EINVAL, "rdcnn_pass_config: NULL argument");
-    int k = h->kind, cpl = h->cpl, d = h->depth, seg = h->seg_rows;
+    int k = h->kind == 3 ? 2 : h->kind, cpl = h->cpl, d = h->depth, seg = h->seg_rows;
     if (h->model != rd::MODEL_FHN) {
         if (k == 0) {
             k = 2;

@@ -29,8 +29,8 @@ class Simulation:
                  tuned: bool = True):
         """tuned: take the forward pass shape the autotuner cached for this grid
         size and boundary rule (tune.py, tuned.json), if there is one; else the
-        library's automatic one.  The setting also applies to the recording
-        calls (capped to what they support)."""
+        library's automatic one.  The recording calls keep their own automatic
+        shapes (rdcnn_set_kernel kind 3)."""
         if x.dim() != 2 or x.dtype != torch.float32 or not x.is_cuda:
             raise ValueError("x must be a 2-D float32 CUDA tensor")
         self.device = x.device
@@ -242,7 +242,9 @@ class Simulation:
     def set_kernel(self, kind: int = 0, depth: int = 0, cols_per_lane: int = 0,
                    seg_rows: int = 0) -> None:
         """0 automatic, 1 one-thread-per-cell reference kernel, 2 streamed kernel
-        with `depth` steps per pass (bit-identical results for every choice)."""
+        with `depth` steps per pass, 3 the same for plain steps only (the
+        recording calls keep their automatic shapes); bit-identical results
+        for every choice."""
         check(lib.rdcnn_set_kernel(self._h, int(kind), int(depth), int(cols_per_lane),
                                    int(seg_rows)))
         self._kernel = (int(kind), int(depth), int(cols_per_lane), int(seg_rows))

@@ -273,7 +273,9 @@ def apply(obj, path: str = None, grad: bool = False, modes=None):
         cfg = lookup(k, path)
         if not cfg:
             continue
-        if mode in ("forward", "record_even"):
+        if mode == "forward":  # plain steps only: recording keeps its own shapes
+            obj.set_kernel(3, *cfg)
+        elif mode == "record_even":
             obj.set_kernel(2, *cfg)
         else:
             obj.set_adjoint_kernel(*cfg)

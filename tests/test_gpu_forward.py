@@ -298,3 +298,24 @@ def test_table1_launch_whole_grid():
     print("case table1 4096^2 periodic T=300", flush=True)
     got = gpu_run(x, g, "periodic", 300)
     _assert_full_grid(got, oracle_run(x, g, "periodic", 300), "table1 4096")
+
+
+def test_plain_only_kernel_setting():
+    """rdcnn_set_kernel kind 3 sets the shape of plain steps (reported by
+    rdcnn_pass_config as a streamed shape) and leaves results bit-identical,
+    also for a recording call in between (which keeps its automatic shape)."""
+    from paper_2102_10340_amd import Simulation
+    R, C = 70, 300
+    x = W.uniform_x(R, C, 12)
+    sim = Simulation(torch.from_numpy(x).cuda(), W.PLAIN_GENE, "zeroflux", tuned=False)
+    sim.set_kernel(3, 4, 2, 8)
+    cfg = sim.pass_config()
+    assert (cfg["kind"], cfg["depth"], cfg["cols_per_lane"], cfg["seg_rows"]) == (2, 4, 2, 8), cfg
+    sim.step(9)
+    st = torch.empty((6, 2, R, C), device="cuda")
+    sim.step_record_even(11, st)
+    sim.step(5)
+    got = sim.read_host()
+    sim.close()
+    want = oracle_run(x, W.PLAIN_GENE, "zeroflux", 25)
+    assert_bitwise(got, want, "kind 3")
