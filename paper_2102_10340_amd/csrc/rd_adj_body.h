@@ -25,6 +25,7 @@
 // adjoint_finish_kernel folds the partials into the eight gradients.
 #pragma once
 
+#include <type_traits>
 #include <utility>
 
 #include "rd_launch.h"
@@ -329,7 +330,9 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
                 load_row<CPL, FAST>(sb, o + pbytes, t, ev[p][(4 * p + q) % NR]);
             }
 
-    auto iteration = [&](const int it, const int S6) __attribute__((always_inline)) {
+    // all: a std::integral_constant<bool, ...>; true in rounds where every
+    // level is already active (it >= 2 KB), which then skip that test.
+    auto iteration = [&](const int it, const int S6, auto all) __attribute__((always_inline)) {
         const int S = S6 % 3;
         // ring slots of rows newest-2 (north), newest-1 (centre), newest (south)
         const int qN = (S6 + NR - 2) % NR, qC = (S6 + NR - 1) % NR, qS = S6;
@@ -351,7 +354,7 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
             // (every iteration of the walk has it < n_real; the tests below
             // are single unsigned compares to keep the scalar unit, which
             // serves a compute unit's four SIMDs, out of the way)
-            if (it >= 2 * i + 2) {
+            if (decltype(all)::value || it >= 2 * i + 2) {
                 float u[CPL], v[CPL];  // the state level i steps back with, row m
                 if (i % 2 == 0) {
                     // O_p row m from E_p rows m-1, m, m+1
@@ -420,11 +423,25 @@ __device__ __forceinline__ void adjoint_pair_body(const AdjArgs &A, const Tile<C
 
     // Iterations from n_real on would only fetch rows nobody reads: leave
     // the unrolled body as soon as the walk is done (uniform branches).
-    for (int it = 0; it < n_real; it += NR) {
+    // Rounds of NR iterations (fully unrolled: every slot index a constant).
+    // From the first round boundary at or after 2 KB on, every level is
+    // active: those rounds run a copy of the body without the per-level
+    // activity tests (one compare and branch per level and iteration saved on
+    // the scalar unit).
+    constexpr int kSteady = (2 * KB + NR - 1) / NR * NR;
+    int it = 0;
+    for (; it < kSteady && it < n_real; it += NR) {
 #pragma unroll
-        for (int q = 0; q < NR; ++q) {  // fully unrolled: every slot index a constant
+        for (int q = 0; q < NR; ++q) {
             if (it + q >= n_real) break;
-            iteration(it + q, q);
+            iteration(it + q, q, std::integral_constant<bool, false>{});
+        }
+    }
+    for (; it < n_real; it += NR) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            if (it + q >= n_real) break;
+            iteration(it + q, q, std::integral_constant<bool, true>{});
         }
     }
     add_tile_sums<CPL, FAST>(A, t, acc);
