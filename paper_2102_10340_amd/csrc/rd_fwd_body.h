@@ -75,6 +75,9 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
     // register copies.
     float l0u[6][CPL], l0v[6][CPL];
     float bu[K][3][CPL], bv[K][3][CPL];  // levels 1 .. K-1 (index 0 unused)
+    // derive(u) of the same rows, in the same slots (kDerived models only)
+    constexpr int KD = M::kDerived ? K : 1;
+    float l0y[M::kDerived ? 6 : 1][CPL], by[KD][3][CPL];
 #pragma unroll
     for (int e = 0; e < CPL; ++e) {
 #pragma unroll
@@ -83,6 +86,14 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
         for (int j = 0; j < K; ++j)
 #pragma unroll
             for (int q = 0; q < 3; ++q) bu[j][q][e] = bv[j][q][e] = 0.0f;
+        if constexpr (M::kDerived) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) l0y[q][e] = 0.0f;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) by[j][q][e] = 0.0f;
+        }
     }
 #pragma unroll
     for (int q = 0; q < kFwdFetch; ++q) {
@@ -96,6 +107,10 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
         // level-0 ring slots of rows it-2 (north), it-1 (centre), it (south)
         const int qN = (S6 + 4) % 6, qC = (S6 + 5) % 6, qS = S6;
         float tu[CPL], tv[CPL];  // row it-K of level K (the pass output)
+        if constexpr (M::kDerived) {
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) l0y[qS][e] = M::derive(l0u[qS][e]);
+        }
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const Slots sl(S, j);
@@ -107,24 +122,31 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
             const float *vN = j == 0 ? l0v[qN] : bv[j][sl.ps];
             const float *vC = j == 0 ? l0v[qC] : bv[j][sl.cs];
             const float *vS = j == 0 ? l0v[qS] : bv[j][sl.ns];
+            // the u layer as the update sees it: derive(u) for kDerived models
+            const float *yN = uN, *yC = uC, *yS = uS;
+            if constexpr (M::kDerived) {
+                yN = j == 0 ? l0y[qN] : by[j][sl.ps];
+                yC = j == 0 ? l0y[qC] : by[j][sl.cs];
+                yS = j == 0 ? l0y[qS] : by[j][sl.ns];
+            }
             // Level j+1 has all three input rows from it = 2j+2 on; rows made
             // after it = n_real are beyond the segment's cone.
             if (it >= 2 * j + 2 && it < n_real) {
                 // lane-shifted edge columns of the centre row (and, for models
                 // reading diagonals, of the north and south rows)
-                const float lu = from_left_lane(uC[CPL - 1]);
-                const float ru = from_right_lane(uC[0]);
+                const float lu = from_left_lane(yC[CPL - 1]);
+                const float ru = from_right_lane(yC[0]);
                 const float lv = from_left_lane(vC[CPL - 1]);
                 const float rv = from_right_lane(vC[0]);
                 float luN = 0.0f, ruN = 0.0f, lvN = 0.0f, rvN = 0.0f;
                 float luS = 0.0f, ruS = 0.0f, lvS = 0.0f, rvS = 0.0f;
                 if (M::kDiag) {
-                    luN = from_left_lane(uN[CPL - 1]);
-                    ruN = from_right_lane(uN[0]);
+                    luN = from_left_lane(yN[CPL - 1]);
+                    ruN = from_right_lane(yN[0]);
                     lvN = from_left_lane(vN[CPL - 1]);
                     rvN = from_right_lane(vN[0]);
-                    luS = from_left_lane(uS[CPL - 1]);
-                    ruS = from_right_lane(uS[0]);
+                    luS = from_left_lane(yS[CPL - 1]);
+                    ruS = from_right_lane(yS[0]);
                     lvS = from_left_lane(vS[CPL - 1]);
                     rvS = from_right_lane(vS[0]);
                 }
@@ -133,25 +155,29 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
                     Nbhd n;
                     n.u = uC[e];
                     n.v = vC[e];
-                    n.uN = uN[e];
-                    n.uS = uS[e];
+                    n.y = yC[e];
+                    n.uN = yN[e];
+                    n.uS = yS[e];
                     n.vN = vN[e];
                     n.vS = vS[e];
-                    n.uW = e == 0 ? lu : uC[e - 1];
-                    n.uE = e == CPL - 1 ? ru : uC[e + 1];
+                    n.uW = e == 0 ? lu : yC[e - 1];
+                    n.uE = e == CPL - 1 ? ru : yC[e + 1];
                     n.vW = e == 0 ? lv : vC[e - 1];
                     n.vE = e == CPL - 1 ? rv : vC[e + 1];
                     if (M::kDiag) {
-                        n.uNW = e == 0 ? luN : uN[e - 1];
-                        n.uNE = e == CPL - 1 ? ruN : uN[e + 1];
+                        n.uNW = e == 0 ? luN : yN[e - 1];
+                        n.uNE = e == CPL - 1 ? ruN : yN[e + 1];
                         n.vNW = e == 0 ? lvN : vN[e - 1];
                         n.vNE = e == CPL - 1 ? rvN : vN[e + 1];
-                        n.uSW = e == 0 ? luS : uS[e - 1];
-                        n.uSE = e == CPL - 1 ? ruS : uS[e + 1];
+                        n.uSW = e == 0 ? luS : yS[e - 1];
+                        n.uSE = e == CPL - 1 ? ruS : yS[e + 1];
                         n.vSW = e == 0 ? lvS : vS[e - 1];
                         n.vSE = e == CPL - 1 ? rvS : vS[e + 1];
                     }
                     M::update(g, n, du[e], dv[e]);
+                    if constexpr (M::kDerived) {
+                        if (j + 1 < K) by[j + 1][sl.cs][e] = M::derive(du[e]);
+                    }
                 }
             }
             // The next level-0 row is loaded before this iteration's stores:

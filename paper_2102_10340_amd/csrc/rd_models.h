@@ -6,6 +6,11 @@
 // a type with
 //   Params                 its parameters (kernel argument, scalar registers)
 //   kDiag                  whether the update reads the diagonal neighbours
+//   kDerived, derive(u)    whether the update sees the u layer only through a
+//                          per-cell function derive(u) (plus the raw centre u):
+//                          the body then forms derive once per row and time
+//                          level and hands it over in the u neighbour fields
+//                          of n, with the centre's in n.y
 //   update(p, n, uo, vo)   the new (u, v) of one cell from its neighbourhood n
 // and the register-streamed body (rd_fwd_body.h) is instantiated per model.
 // Every model fixes its float32 rounding order; the CPU oracle writes the same
@@ -23,9 +28,11 @@
 
 namespace rd {
 
-// Centre and neighbours of both layers (the diagonals only for kDiag models).
+// Centre and neighbours of both layers (the diagonals only for kDiag models;
+// for kDerived models the u neighbour fields hold derive(u), and y the
+// centre's derive(u)).
 struct Nbhd {
-    float u, v;
+    float u, v, y;
     float uN, uS, uW, uE, vN, vS, vW, vE;
     float uNW, uNE, uSW, uSE, vNW, vNE, vSW, vSE;
 };
@@ -34,6 +41,7 @@ struct Nbhd {
 struct ModelFHN {
     using Params = Gene;
     static constexpr bool kDiag = false;
+    static constexpr bool kDerived = false;
     __device__ __forceinline__ static void update(const Gene &g, const Nbhd &n, float &uo, float &vo)
     {
         cell_update(g, n.u, n.v, n.uN, n.uS, n.uW, n.uE, n.vN, n.vS, n.vW, n.vE, uo, vo);
@@ -51,6 +59,7 @@ struct GrayScottParams {
 struct ModelGrayScott {
     using Params = GrayScottParams;
     static constexpr bool kDiag = false;
+    static constexpr bool kDerived = false;
     __device__ __forceinline__ static void update(const Params &p, const Nbhd &n, float &uo, float &vo)
     {
         const float sU = (n.uN + n.uS) + (n.uW + n.uE);
@@ -91,14 +100,16 @@ __device__ __forceinline__ float template3(const float *T, float nw, float n, fl
            T[4] * c;
 }
 
+// The outputs y are formed once per cell and level (kDerived), not once per
+// template tap: the same function of the same value, so the same bits.
 struct ModelCnn {
     using Params = CnnParams;
     static constexpr bool kDiag = true;
+    static constexpr bool kDerived = true;
+    __device__ __forceinline__ static float derive(float x) { return cnn_out(x); }
     __device__ __forceinline__ static void update(const Params &p, const Nbhd &n, float &uo, float &vo)
     {
-        const float ay = template3(p.A, cnn_out(n.uNW), cnn_out(n.uN), cnn_out(n.uNE),
-                                   cnn_out(n.uW), cnn_out(n.u), cnn_out(n.uE), cnn_out(n.uSW),
-                                   cnn_out(n.uS), cnn_out(n.uSE));
+        const float ay = template3(p.A, n.uNW, n.uN, n.uNE, n.uW, n.y, n.uE, n.uSW, n.uS, n.uSE);
         uo = __builtin_fmaf(p.dt, (ay + n.v) - n.u, n.u);
         vo = n.v;
     }
