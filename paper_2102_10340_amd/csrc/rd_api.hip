@@ -1060,10 +1060,19 @@ int rdcnn_step_bwd_ckpt(rdcnn_t h, const float *ckpt_dev, long long T, long long
     if (!even_record_shape(h, 2, &cpl, &depth, &seg))
         return fail(RDCNN_EINVAL, "%s: grid too large to record", who);
     // The recompute shares the GPU with the reverse passes of the next
-    // segment, so it gets half the wavefronts of a recording run alone
-    // (segments twice as tall, less halo work): 14.9 against 15.4 ms for
-    // 1024^2, T = 2000, in a sweep over 8 to 32 rows.
-    if (h->kind != 2) seg *= 2;
+    // segment, so it aims at ~940 wavefronts, a third of what a recording run
+    // alone aims at (taller segments, less halo work; never shorter ones than
+    // alone).  On 1024^2, T = 2000 (22 strips: 24-row segments) the backward
+    // took 10.0 ms against 10.3 at 16 rows and 10.6 at 8, in a sweep over 8
+    // to 32 rows.
+    if (h->kind != 2) {
+        rd::StreamGeom sg;
+        if (rd::stream_geometry(h->R, h->C, cpl, depth, seg, &sg)) {
+            const long long per_strip = (940 + sg.nstrips - 1) / sg.nstrips;
+            const long long rows = (h->R + per_strip - 1) / per_strip;
+            if (rows > seg) seg = (int)rows;
+        }
+    }
     // One partial buffer for every segment: cleared once, folded once.
     const long long Llast = T - (nseg - 1) * S;
     PairPlan pl, plast;

@@ -13,6 +13,8 @@
 // neighbours get them from DPP shifts of the north and south rows.
 #pragma once
 
+#include <type_traits>
+
 #include "rd_models.h"
 #include "rd_stream.h"
 
@@ -102,7 +104,18 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
         load_row<CPL, FAST>(iv, ro, t, l0v[q]);
     }
 
-    auto iteration = [&](const int it, const int S6) __attribute__((always_inline)) {
+    // Row m is an output row of the tile.  The recording passes test it with
+    // one unsigned compare (their scalar unit is the busier one); the plain
+    // pass keeps the two signed ones it was tuned with.
+    auto inside = [&](const int m) __attribute__((always_inline)) {
+        return REC ? (unsigned)(m - y0) < (unsigned)(y1 - y0) : (m >= y0 && m < y1);
+    };
+
+    // all: every level is active (it >= 2K); the recording passes run their
+    // rounds past the pipeline fill with this set, which drops the per-level
+    // activity tests.
+    auto iteration = [&](const int it, const int S6, auto all) __attribute__((always_inline)) {
+        constexpr bool kAll = decltype(all)::value;
         const int S = S6 % 3;
         // level-0 ring slots of rows it-2 (north), it-1 (centre), it (south)
         const int qN = (S6 + 4) % 6, qC = (S6 + 5) % 6, qS = S6;
@@ -131,7 +144,7 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
             }
             // Level j+1 has all three input rows from it = 2j+2 on; rows made
             // after it = n_real are beyond the segment's cone.
-            if (it >= 2 * j + 2 && it < n_real) {
+            if (kAll || (it >= 2 * j + 2 && it < n_real)) {
                 // lane-shifted edge columns of the centre row (and, for models
                 // reading diagonals, of the north and south rows)
                 const float lu = from_left_lane(yC[CPL - 1]);
@@ -191,17 +204,17 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
                 load_row<CPL, FAST>(iv, ro, t, l0v[(S6 + kFwdFetch) % 6]);
                 if (REC == 1 || REC == 2) {
                     const int m = rbase + it;  // level-0 row it
-                    if (m >= y0 && m < y1) {
+                    if (inside(m)) {
                         const unsigned o = 4u * (unsigned)m * C;
                         store_row<CPL, FAST>(rb, o, C, t, l0u[qS]);
                         store_row<CPL, FAST>(rb, o + pbytes, C, t, l0v[qS]);
                     }
                 }
             }
-            if (REC && j + 1 < K && (REC == 1 || (j + 1) % 2 == 0) && it >= 2 * j + 2 &&
-                it < n_real) {
+            if (REC && j + 1 < K && (REC == 1 || (j + 1) % 2 == 0) &&
+                (kAll || (it >= 2 * j + 2 && it < n_real))) {
                 const int m = rbase + it - j - 1;  // level-(j+1) row just made
-                if (m >= y0 && m < y1) {
+                if (inside(m)) {
                     const unsigned o = (unsigned)(REC >= 2 ? (j + 1) / 2 : j + 1) * rstride +
                                        4u * (unsigned)m * C;
                     store_row<CPL, FAST>(rb, o, C, t, bu[j + 1][sl.cs]);
@@ -210,7 +223,7 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
             }
         }
         const int m = rbase + it - K;  // row of level K now in (tu, tv)
-        if (m >= y0 && m < y1) {
+        if (inside(m)) {
             const unsigned o = 4u * (unsigned)m * C;
             store_row<CPL, FAST>(ou, o, C, t, tu);
             store_row<CPL, FAST>(ov, o, C, t, tv);
@@ -219,18 +232,40 @@ __device__ __forceinline__ void stream_body(const StreamArgsT<M> &A, const Tile<
 
     // Iterations from n_real on would only fetch rows nobody reads: leave the
     // unrolled body as soon as the walk is done (uniform branches).
-    for (int it = 0; it < n_real; it += 6) {
-        iteration(it, 0);
-        if (it + 1 >= n_real) break;
-        iteration(it + 1, 1);
-        if (it + 2 >= n_real) break;
-        iteration(it + 2, 2);
-        if (it + 3 >= n_real) break;
-        iteration(it + 3, 3);
-        if (it + 4 >= n_real) break;
-        iteration(it + 4, 4);
-        if (it + 5 >= n_real) break;
-        iteration(it + 5, 5);
+    const std::integral_constant<bool, false> ramp{};
+    if constexpr (REC == 0) {
+        for (int it = 0; it < n_real; it += 6) {
+            iteration(it, 0, ramp);
+            if (it + 1 >= n_real) break;
+            iteration(it + 1, 1, ramp);
+            if (it + 2 >= n_real) break;
+            iteration(it + 2, 2, ramp);
+            if (it + 3 >= n_real) break;
+            iteration(it + 3, 3, ramp);
+            if (it + 4 >= n_real) break;
+            iteration(it + 4, 4, ramp);
+            if (it + 5 >= n_real) break;
+            iteration(it + 5, 5, ramp);
+        }
+    } else {
+        // every level is active from it = 2K on; the rounds from the first
+        // multiple of six past that run the copy without the tests
+        constexpr int kSteady = (2 * K + 5) / 6 * 6;
+        int it = 0;
+        for (; it < kSteady && it < n_real; it += 6) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                if (it + q >= n_real) break;
+                iteration(it + q, q, ramp);
+            }
+        }
+        for (; it < n_real; it += 6) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                if (it + q >= n_real) break;
+                iteration(it + q, q, std::integral_constant<bool, true>{});
+            }
+        }
     }
 }
 
