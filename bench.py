@@ -558,6 +558,28 @@ def oracle_workloads(gpu_plain_state=None):
     return out
 
 
+def copy_ceiling(dev) -> float:
+    """Attainable HBM rate on this GPU: a plain 512 MiB device copy (torch's
+    copy kernel), best of five, counting the bytes read and written."""
+    import torch
+    n = (512 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    return 2 * n * 4 / (best / 1e3) / 1e9
+
+
 def main():
     args = parse()
     plain_state = None
@@ -664,6 +686,13 @@ def main():
         "final_max_abs_u": alive,
     }
     sim.close()
+    copy_gbs = copy_ceiling(dev)
+    out["roofline"]["copy_ceiling"] = {
+        "basis": "best of 5 device-to-device copies of 512 MiB (read + write bytes / time)",
+        "gbs": copy_gbs, "frac_of_peak": copy_gbs / HBM_PEAK_GBS}
+    if out["roofline"]["measured_hbm"] is not None:
+        out["roofline"]["measured_hbm"]["frac_of_copy"] = (
+            out["roofline"]["measured_hbm"]["gbs"] / copy_gbs)
     if not args.no_extra:
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
