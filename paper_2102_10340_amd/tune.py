@@ -305,6 +305,10 @@ if __name__ == "__main__":
         for n in (4096, 1024, 512, 256, 128):
             best, res = tune("forward", n, n, a.bc, budget_s=a.budget)
             print("forward", n, "best", best, f"{res[best]:.1f} Gcell/s", flush=True)
+        # and the paper's Table I sweep (periodic grids, N = 128 ... 4096)
+        for n in (4096, 2048, 1024, 512, 256, 128):
+            best, res = tune("forward", n, n, "periodic", budget_s=a.budget)
+            print("forward periodic", n, "best", best, f"{res[best]:.1f} Gcell/s", flush=True)
         a.mode = "batch-sweep"
     if a.mode == "batch-sweep":
         # the 1024-instance parameter-sweep workload (seeded synthetic inputs)
