@@ -290,8 +290,13 @@ void auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows, bool r
         if (want < 1) want = 1;
         long long seg = (h->R + want - 1) / want;
         *seg_rows = (int)(seg < 4 ? 4 : seg);
-    } else if (h->R >= 2048 && h->C >= 2048) {
+    } else if (h->R >= 3072 && h->C >= 3072) {
         *cpl = 4;
+        *depth = 8;
+    } else if (h->R >= 2048 && h->C >= 2048) {
+        // four columns per lane leave too few wavefronts below ~3072^2:
+        // 992 against 802 Gcell-updates/s at 2048^2, 1150 against 1063 at 2560^2
+        *cpl = 2;
         *depth = 8;
     } else {
         *cpl = 1;
