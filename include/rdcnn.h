@@ -324,9 +324,12 @@ int rdcnn_step_bwd(rdcnn_t h, float *states_dev, long long S, float *lam_dev, fl
  * checkpoint, re-run the segment recording the states of its even times
  * (rdcnn_step_record_sparse's layout) and run the reverse passes of
  * rdcnn_step_bwd through it.  The recompute of segment k runs on a second
- * stream (made by the library on first use, default priority, destroyed with
- * the handle) while the reverse passes of segment k+1 run on the handle's
- * stream; the two alternate between the two halves of work_dev.  The partial
+ * stream while the reverse passes of segment k+1 run on the handle's stream;
+ * the two alternate between the two halves of work_dev.  The second stream is
+ * the device's: made by the library on first use (default priority), shared by
+ * every handle on that device (each orders its own work on it with its own
+ * events) and kept until the process ends; rdcnn_destroy waits for the
+ * handle's work on it.  The partial
  * sums of all segments go to one buffer, folded once at the end.
  *   ckpt_dev     device, ceil(T/S) states of 2*rows*cols floats: checkpoint j =
  *                s_{t0+jS} (read only)

@@ -33,7 +33,7 @@ struct rdcnn_sim {
     float mparams[rd::kModelParams];       // parameters of the other models
     int check_finite;                      // rdcnn_read checks the state for NaN / Inf
     int *finite_flag;                      // device counter of that check (made on first use)
-    hipStream_t side;                      // rdcnn_step_bwd_ckpt's recompute stream (made on first use)
+    hipStream_t side;                      // rdcnn_step_bwd_ckpt's recompute stream (the device's, see side_stream)
     hipEvent_t ev[5];                      // its events: ready[2], done[2], start
     int use_graph;                         // rdcnn_step replays captured launch sequences
     struct StepGraph {
@@ -195,6 +195,33 @@ int scratch_address(double **out, const char *who)
         g_scratch_dev[dev] = (double *)p;
     }
     *out = g_scratch_dev[dev];
+    return RDCNN_OK;
+}
+
+// The recompute stream of rdcnn_step_bwd_ckpt: one per device, made on first
+// use and kept until the process ends.  Making a stream takes ~70 us of host
+// time, which a handle per autograd call would otherwise pay in every
+// backward.  Handles on a device share it; each orders its own recomputes with
+// its own events, so one handle's recomputes only queue behind another's.
+std::mutex g_side_mu;
+hipStream_t g_side[kMaxDevices];
+
+int side_stream(hipStream_t *out, const char *who)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, who);
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(RDCNN_EINVAL, "%s: device %d beyond the %d the stream table holds", who, dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    if (!g_side[dev]) {
+        hipStream_t s = nullptr;
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, who);
+        g_side[dev] = s;
+    }
+    *out = g_side[dev];
     return RDCNN_OK;
 }
 
@@ -1087,18 +1114,13 @@ int rdcnn_step_bwd_ckpt(rdcnn_t h, const float *ckpt_dev, long long T, long long
     const long long need = pl.need > plast.need ? pl.need : plast.need;
     if ((rc = ensure_partial(h, need, who)) != RDCNN_OK) return rc;
     hipError_t e = hipSuccess;
-    if (!h->side) {
-        e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+    if (!h->side && (rc = side_stream(&h->side, who)) != RDCNN_OK) return rc;
+    for (hipEvent_t &ev : h->ev) {
+        if (ev) continue;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e != hipSuccess) {
-            h->side = nullptr;
+            ev = nullptr;
             return hip_fail(e, who);
-        }
-        for (hipEvent_t &ev : h->ev) {
-            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-            if (e != hipSuccess) {
-                ev = nullptr;
-                return hip_fail(e, who);
-            }
         }
     }
     hipEvent_t *ready = h->ev, *done = h->ev + 2, start = h->ev[4];
@@ -1268,10 +1290,11 @@ int rdcnn_destroy(rdcnn_t h)
     if (!h) return RDCNN_OK;
     pool_put(h->partial_device, h->partial_cap, h->partial, h->stream);
     if (h->finite_flag) (void)hipFree(h->finite_flag);
-    if (h->side) {
-        (void)hipStreamSynchronize(h->side);
-        (void)hipStreamDestroy(h->side);
-    }
+    // The recompute stream is the device's and stays; wait for this handle's
+    // recomputes on it (each ends with one of its events) before the caller
+    // may free the buffers they use.
+    for (hipEvent_t e : h->ev)
+        if (e) (void)hipEventSynchronize(e);
     for (hipEvent_t e : h->ev)
         if (e) (void)hipEventDestroy(e);
     drop_graphs(h);
