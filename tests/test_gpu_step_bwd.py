@@ -178,6 +178,53 @@ def test_step_bwd_ckpt_through_cabi(bc, T, S):
         assert abs(got_p[i] - dp[k]) <= 1e-3 * max(abs(dp[k]), 1e-3 * scale), (k, got_p[i], dp[k])
 
 
+def test_step_bwd_ckpt_two_handles_share_the_recompute_stream():
+    """Two handles on two streams of one device run rdcnn_step_bwd_ckpt back to
+    back with no synchronisation between the calls.  The recompute stream is
+    the device's and both queue their recomputes on it; each result is bit for
+    bit what the same handle gives when it runs alone."""
+    from paper_2102_10340_amd._lib import check, lib
+    cases = [(70, 130, "zeroflux", 41, 9), (96, 64, "periodic", 60, 16)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    rng = np.random.default_rng(7)
+    setups = []
+    for (R, C, bc, T, S), s in zip(cases, streams):
+        with torch.cuda.stream(s):
+            g = _gene(bc)
+            x = W.uniform_x(R, C, T + S)
+            sim = _sim(x, g, bc)
+            nseg = -(-T // S)
+            ckpt = torch.empty((nseg, 2, R, C), device="cuda")
+            sim.step_checkpoints(T, S, ckpt)
+            lam0 = torch.from_numpy(rng.standard_normal((R, C)).astype(np.float32)).cuda()
+            mu0 = torch.from_numpy(rng.standard_normal((R, C)).astype(np.float32)).cuda()
+            work = torch.empty((2 * (min(S, T) + 1), 2, R, C), device="cuda")
+            setups.append((sim, s, ckpt, T, S, work, lam0, mu0))
+    torch.cuda.synchronize()
+
+    def run(sim, s, ckpt, T, S, work, lam0, mu0):
+        with torch.cuda.stream(s):
+            lam, mu = lam0.clone(), mu0.clone()
+            dth = torch.zeros(8, dtype=torch.float64, device="cuda")
+            check(lib.rdcnn_step_bwd_ckpt(sim._h, ckpt.data_ptr(), T, S, work.data_ptr(),
+                                          lam.data_ptr(), mu.data_ptr(), dth.data_ptr()))
+        return lam, mu, dth
+
+    alone = []
+    for st in setups:
+        alone.append(run(*st))
+        torch.cuda.synchronize()
+    for rep in range(3):
+        print(f"case two handles, shared recompute stream, rep {rep}", flush=True)
+        together = [run(*st) for st in setups]  # queued back to back, no sync
+        torch.cuda.synchronize()
+        for a, b in zip(alone, together):
+            for u, v in zip(a, b):
+                assert torch.equal(u, v)
+    for st in setups:
+        st[0].close()
+
+
 def test_step_bwd_ckpt_rejects_bad_arguments():
     from paper_2102_10340_amd._lib import EINVAL, lib
     R, C, T, S = 16, 20, 12, 4
