@@ -118,7 +118,8 @@ enum {
  * rdcnn_step, rdcnn_read, rdcnn_write_state, rdcnn_current, rdcnn_set_kernel
  * (kind 0, 2 or 3) and rdcnn_destroy apply as for rdcnn_create's grids; models
  * other than FitzHugh-Nagumo use passes of 1, 2, 4 or 8 steps and 1 or 2
- * columns per lane, and have no reverse pass (rdcnn_step_record,
+ * columns per lane (Gray-Scott also 4; a wider setting runs at the model's
+ * widest), and have no reverse pass (rdcnn_step_record,
  * rdcnn_adjoint and rdcnn_set_params return RDCNN_EINVAL for them).
  * u0_dev, v0_dev: device, rows*cols floats each; buf0/buf1 as for rdcnn_create.
  * Errors: RDCNN_EINVAL (unknown model, wrong parameter count, non-finite

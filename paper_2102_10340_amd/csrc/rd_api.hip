@@ -334,17 +334,30 @@ void auto_config(const rdcnn_sim *h, int *cpl, int *depth, int *seg_rows, bool r
 // Steps of a model other than FitzHugh-Nagumo: passes of 8, 4, 2 or 1 steps
 // (the instantiated depths), one step per pass at a zero-flux edge when the
 // update is not mirror-exact for these parameters.
+// Pass shape of a grid of another cell model: the forced settings, else 8
+// steps per pass with 4 columns per lane from 3072^2 (models instantiated
+// that wide), 2 from 2048^2, 1 below; widths beyond the model's widest are
+// narrowed to it.
+void model_shape(const rdcnn_sim *h, int *cpl, int *depth, int *seg)
+{
+    const int wmax = rd::model_max_cpl(h->model);
+    *cpl = h->cpl;
+    *depth = h->depth;
+    *seg = h->seg_rows;
+    if (h->kind == 0) {
+        *cpl = h->R >= 3072 && h->C >= 3072 ? 4 : h->R >= 2048 && h->C >= 2048 ? 2 : 1;
+        *depth = 8;
+        *seg = 0;
+    }
+    if (*cpl > wmax) *cpl = wmax;
+}
+
 int run_model_steps(rdcnn_sim *h, long long n)
 {
     if (h->kind == 1) return fail(RDCNN_EINVAL, "rdcnn_step: the one-thread-per-cell kernel "
                                                 "exists for FitzHugh-Nagumo only");
-    int cpl = h->cpl, depth = h->depth, seg = h->seg_rows;
-    if (h->kind == 0) {
-        cpl = h->R >= 2048 && h->C >= 2048 ? 2 : 1;
-        depth = 8;
-        seg = 0;
-    }
-    if (cpl > 2) cpl = 2;
+    int cpl, depth, seg;
+    model_shape(h, &cpl, &depth, &seg);
     if (h->bc == RDCNN_BC_ZEROFLUX && !rd::model_mirror_exact(h->model, h->mparams)) depth = 1;
     while (n > 0) {
         int k = 8;
@@ -1258,13 +1271,8 @@ int rdcnn_pass_config(rdcnn_t h, int *kind, int *depth, int *cols_per_lane, int 
         return fail(RDCNN_EINVAL, "rdcnn_pass_config: NULL argument");
     int k = h->kind == 3 ? 2 : h->kind, cpl = h->cpl, d = h->depth, seg = h->seg_rows;
     if (h->model != rd::MODEL_FHN) {
-        if (k == 0) {
-            k = 2;
-            cpl = h->R >= 2048 && h->C >= 2048 ? 2 : 1;
-            d = 8;
-            seg = 0;
-        }
-        if (cpl > 2) cpl = 2;
+        if (k == 0) k = 2;
+        model_shape(h, &cpl, &d, &seg);
     } else if (k == 0) {
         k = 2;
         auto_config(h, &cpl, &d, &seg, false);

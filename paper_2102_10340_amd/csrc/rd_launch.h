@@ -77,7 +77,8 @@ hipError_t launch_stream(const float *in, float *out, int R, int C, int bc, cons
                          int rec_every = 1);
 
 // Cell models other than FitzHugh-Nagumo on the same streamed kernel
-// (rd_models.h).  Their passes take depth 1, 2, 4 or 8 and cols_per_lane 1 or 2.
+// (rd_models.h).  Their passes take depth 1, 2, 4 or 8 and cols_per_lane 1, 2
+// or, for models instantiated that wide (model_max_cpl), 4.
 enum { MODEL_FHN = 0, MODEL_GRAY_SCOTT = 1, MODEL_CNN = 2 };
 constexpr int kModelParams = 20;  // largest parameter vector (CNN: dt, A[9], B[9], z)
 inline int model_nparams(int model)
@@ -86,6 +87,8 @@ inline int model_nparams(int model)
 }
 // Whether blocked passes are exact at a zero-flux edge for these parameters.
 bool model_mirror_exact(int model, const float *params);
+// The widest strip a model is instantiated for (columns per lane: 2 or 4).
+int model_max_cpl(int model);
 hipError_t launch_model(int model, const float *in, float *out, int R, int C, int bc,
                         const float *params, const StreamGeom &geom, hipStream_t s);
 // CNN input layer: w = (B * img) + z (bz = B[9], z), with the grid's boundary rule.

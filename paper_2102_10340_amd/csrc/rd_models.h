@@ -60,6 +60,7 @@ struct ModelGrayScott {
     using Params = GrayScottParams;
     static constexpr bool kDiag = false;
     static constexpr bool kDerived = false;
+    static constexpr int kMaxCpl = 4;  // widest strip instantiated (columns per lane)
     __device__ __forceinline__ static void update(const Params &p, const Nbhd &n, float &uo, float &vo)
     {
         const float sU = (n.uN + n.uS) + (n.uW + n.uE);
@@ -106,6 +107,7 @@ struct ModelCnn {
     using Params = CnnParams;
     static constexpr bool kDiag = true;
     static constexpr bool kDerived = true;
+    static constexpr int kMaxCpl = 2;  // four columns would not fit the 256 VGPRs
     __device__ __forceinline__ static float derive(float x) { return cnn_out(x); }
     __device__ __forceinline__ static void update(const Params &p, const Nbhd &n, float &uo, float &vo)
     {

@@ -60,6 +60,13 @@ ModelFn<M> pick_model(int cpl, int depth)
         if (depth == 2) return &model_step_kernel<M, 2, 2>;
         if (depth == 4) return &model_step_kernel<M, 2, 4>;
         if (depth == 8) return &model_step_kernel<M, 2, 8>;
+    } else if (cpl == 4) {
+        if constexpr (M::kMaxCpl >= 4) {
+            if (depth == 1) return &model_step_kernel<M, 4, 1>;
+            if (depth == 2) return &model_step_kernel<M, 4, 2>;
+            if (depth == 4) return &model_step_kernel<M, 4, 4>;
+            if (depth == 8) return &model_step_kernel<M, 4, 8>;
+        }
     }
     return nullptr;
 }
@@ -82,6 +89,13 @@ hipError_t launch_as(const float *in, float *out, int R, int C, int bc,
 }
 
 }  // namespace
+
+int model_max_cpl(int model)
+{
+    return model == MODEL_GRAY_SCOTT ? ModelGrayScott::kMaxCpl
+           : model == MODEL_CNN      ? ModelCnn::kMaxCpl
+                                     : 0;
+}
 
 bool model_mirror_exact(int model, const float *p)
 {

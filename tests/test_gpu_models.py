@@ -49,9 +49,15 @@ def _run(sim, T, kernel, chunks=None):
     return out
 
 
-@pytest.mark.parametrize("kernel", KERNELS, ids=lambda k: "auto" if k is None else "d%d_c%d_h%d" % k[1:])
+# Gray-Scott is also instantiated four columns per lane wide; (40, 1024) has
+# whole-width vector strips at that width.
+GS_KERNELS = KERNELS + [(2, 8, 4, 0), (2, 3, 4, 5), (2, 4, 4, 0)]
+GS_SHAPES = SHAPES + [(40, 1024)]
+
+
+@pytest.mark.parametrize("kernel", GS_KERNELS, ids=lambda k: "auto" if k is None else "d%d_c%d_h%d" % k[1:])
 @pytest.mark.parametrize("bc", BCS)
-@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "%dx%d" % s)
+@pytest.mark.parametrize("shape", GS_SHAPES, ids=lambda s: "%dx%d" % s)
 def test_gray_scott_bitwise(shape, bc, kernel):
     from paper_2102_10340_amd import Simulation
     R, C = shape
@@ -136,6 +142,27 @@ def test_gray_scott_full_size():
     got = _run(Simulation.gray_scott(_t(u0), _t(v0), bc="periodic", **GS), 200, None)
     want = oracle.gs_run(u0, v0, GS, "periodic", 200)
     assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+
+
+def test_gray_scott_wide_strips_full_size():
+    """3072x3072 Gray-Scott, 64 steps, default pass settings (four columns per
+    lane from 3072^2 on): whole grid bit for bit against the oracle; the CNN
+    asked for four columns runs two (its widest) and stays bitwise too."""
+    from paper_2102_10340_amd import Simulation
+    u0, v0 = _gs_init(3072, 3072, 9)
+    sim = Simulation.gray_scott(_t(u0), _t(v0), bc="zeroflux", **GS)
+    assert sim.pass_config()["cols_per_lane"] == 4
+    got = _run(sim, 64, None)
+    want = oracle.gs_run(u0, v0, GS, "zeroflux", 64)
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+    img = W.uniform_x(64, 300, 4)
+    cnn = Simulation.cnn(_t(np.zeros_like(img)), _t(img), SYM_A, B, -0.5, 0.1, "zeroflux")
+    cnn.set_kernel(2, 8, 4, 0)
+    assert cnn.pass_config()["cols_per_lane"] == 2
+    got = _run(cnn, 19, None)
+    want = oracle.cnn_run(np.zeros_like(img), oracle.cnn_input(img, B, -0.5, "zeroflux"), 0.1, SYM_A,
+                          "zeroflux", 19)
+    assert np.array_equal(got[0], want)
 
 
 def test_model_grids_reject_fhn_only_calls():
