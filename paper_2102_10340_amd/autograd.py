@@ -143,7 +143,7 @@ class RDCNNFunction(torch.autograd.Function):
         T = int(T)
         S = choose_schedule(T, x.shape[0], x.shape[1], int(S), x.device)
         record = bool(ctx.needs_input_grad[0] or ctx.needs_input_grad[1])
-        sim = Simulation(x, _gene(theta), bc, ka, tuned=False)
+        sim = Simulation(x, _gene(theta), bc, ka, tuned=True)
         u, v, ckpt, nseg = _forward(sim, T, S, x.device, record)
         if not record:
             sim.close()
@@ -176,7 +176,7 @@ class RDCNNStateFunction(torch.autograd.Function):
         T = int(T)
         S = choose_schedule(T, u0.shape[0], u0.shape[1], int(S), u0.device)
         record = bool(any(ctx.needs_input_grad[:3]))
-        sim = Simulation.from_state(u0, v0, _gene(theta), bc, tuned=False)
+        sim = Simulation.from_state(u0, v0, _gene(theta), bc, tuned=True)
         u, v, ckpt, nseg = _forward(sim, T, S, u0.device, record)
         if not record:
             sim.close()
