@@ -1107,9 +1107,9 @@ int rdcnn_step_bwd_ckpt(rdcnn_t h, const float *ckpt_dev, long long T, long long
     // The recompute shares the GPU with the reverse passes of the next
     // segment, so it aims at ~940 wavefronts, a third of what a recording run
     // alone aims at (taller segments, less halo work; never shorter ones than
-    // alone).  On 1024^2, T = 2000 (22 strips: 24-row segments) the backward
-    // took 10.0 ms against 10.3 at 16 rows and 10.6 at 8, in a sweep over 8
-    // to 32 rows.
+    // alone), in passes of 6 steps.  On 1024^2, T = 2000 (22 strips: 24-row
+    // segments) the backward took 9.96 ms against 10.06 at 8 steps, 10.3 at
+    // 16 rows and 10.6 at 8 rows, in sweeps over 8 to 32 rows.
     if (h->kind != 2) {
         rd::StreamGeom sg;
         if (rd::stream_geometry(h->R, h->C, cpl, depth, seg, &sg)) {
@@ -1117,6 +1117,7 @@ int rdcnn_step_bwd_ckpt(rdcnn_t h, const float *ckpt_dev, long long T, long long
             const long long rows = (h->R + per_strip - 1) / per_strip;
             if (rows > seg) seg = (int)rows;
         }
+        if (depth > 6) depth = 6;
     }
     // One partial buffer for every segment: cleared once, folded once.
     const long long Llast = T - (nseg - 1) * S;
